@@ -1,0 +1,128 @@
+/*
+ * fock.h -- C ABI of the exact-exchange (Fock) band-pair path on one MI355X.
+ *
+ * The operation (Varini et al., "Enhancement of DFT-calculations at
+ * Petascale", section 4): for occupied orbitals phi_i with weights f_i and
+ * target orbitals psi_j, all given as plane-wave coefficients on one G-sphere,
+ *
+ *   (V_x psi_j)(G) = - sum_i f_i sum_{G1} c_i(G1) v_ij(G - G1),    G in sphere
+ *   v_ij(G)        = K(q+G) rho_ij(G),   K(q+G) = 4 pi / |q+G|^2
+ *   rho_ij(G)      = Omega^-1 sum_{G1} conj(c_i(G1)) d_j(G1 + G)
+ *
+ * i.e. the action of the exchange operator of section 4 (V_x applied to a
+ * state, with the overlap charge densities M of the reciprocal-space
+ * exchange-energy formula), computed through real space with FFTs as that
+ * section describes:  (V_x psi_j) = -(1/(Omega N^2)) sum_i f_i
+ * FFT[ phi~_i * BFFT[ K * FFT[ conj(phi~_i) psi~_j ] ] ] on the sphere, with
+ * phi~ = BFFT(sphere coefficients), FFT = sum_r e^{-iG.r}, BFFT = sum_G
+ * e^{+iG.r}, both unnormalised, N = n1 n2 n3 grid points.
+ *
+ * Units: Hartree atomic units (bohr, bohr^-1, Hartree).
+ * q is the Bloch-vector difference k_target - k_occupied (Cartesian bohr^-1).
+ * The single point q + G = 0 (q = 0, G = 0) takes K = 0 (FOCK_G0_ZERO) or the
+ * Gygi-Baldereschi constant K0 of the cell's Gamma-centred nq mesh with
+ * auxiliary width gb_alpha (FOCK_G0_GB).
+ *
+ * Memory: orbital coefficients, weights, outputs, workspace and device scalars
+ * are DEVICE pointers owned by the caller; fock_cell and its Miller list are
+ * HOST memory read during the call only.  Complex data is interleaved
+ * (re, im) in the precision the dtype names: complex128 for FOCK_C128 (the
+ * FP64 path), complex64 for FOCK_C64 (FP32 transforms and products, FP64
+ * energy reduction and G = 0 constant).  Weights and scalars are always FP64.
+ * All work is enqueued on `stream` (a hipStream_t; NULL = the null stream);
+ * no call synchronises the host.  Calls that share a workspace must not
+ * overlap.
+ *
+ * Errors: arguments are validated on the host before anything is enqueued;
+ * on error nothing is written and a status < 0 is returned, with a detail
+ * string from fock_last_error() (thread local).  FOCK_E_HIP reports a failed
+ * launch; faults of enqueued work surface at the caller's next synchronise.
+ */
+#ifndef FOCK_H
+#define FOCK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  FOCK_OK = 0,
+  FOCK_E_ARG = -1,              /* null pointer, negative count, ld < npw, bad cell ... */
+  FOCK_E_ALIAS = -2,            /* a Miller index |m_a| > (n_a - 1) / 4, or a repeated G */
+  FOCK_E_SINGULAR_Q = -3,       /* q != 0 but q + G = 0 for a reciprocal-lattice vector G */
+  FOCK_E_WORKSPACE = -4,        /* workspace missing or smaller than fock_workspace_size */
+  FOCK_E_UNSUPPORTED_GRID = -5, /* grid shape without compiled transforms */
+  FOCK_E_HIP = -6               /* a HIP runtime call failed */
+} fock_status;
+
+typedef enum { FOCK_C128 = 0, FOCK_C64 = 1 } fock_dtype;
+typedef enum { FOCK_G0_ZERO = 0, FOCK_G0_GB = 1 } fock_g0;
+
+/* The cell, FFT grid and G-sphere (host memory). */
+typedef struct {
+  double a[3][3];          /* lattice vectors a_1, a_2, a_3 as rows, bohr */
+  int32_t n[3];            /* FFT grid n1 x n2 x n3; box is C order, i3 fastest */
+  int32_t npw;             /* number of sphere plane waves */
+  const int32_t *miller;   /* [npw][3] signed Miller indices, |m_a| <= (n_a - 1) / 4 */
+  double ecut_fock;        /* cutoff on |q+G|^2 (bohr^-2) for K; <= 0: whole box */
+  int32_t g0;              /* fock_g0 */
+  double gb_alpha;         /* FOCK_G0_GB: auxiliary width alpha, bohr^2 (> 0) */
+  int32_t nq[3];           /* FOCK_G0_GB: Gamma-centred mesh of the q sum (>= 1) */
+} fock_cell;
+
+/* A block of orbitals (device memory). */
+typedef struct {
+  const void *c;           /* [nb][ld] complex coefficients, in sphere order */
+  const double *w;         /* [nb] FP64 occupations (occupied) or weights (targets) */
+  int32_t nb;              /* number of orbitals (>= 0) */
+  int32_t ld;              /* leading dimension in complex elements (>= npw) */
+} fock_orbs;
+
+/* Bytes of device workspace needed by every call below for these sizes. */
+size_t fock_workspace_size(const fock_cell *cell, int32_t dtype, int32_t n_occ, int32_t n_tgt);
+
+/* Exchange operator applied to the targets (section 4, V_x on a state):
+ * vx_out[j][p] = (V_x psi_j)(G_p), p < npw, device [tgt.nb][tgt.ld]; entries
+ * p >= npw are left untouched.  occ.w are the occupations f_i; tgt.w is not
+ * read.  The band-pair loop is tiled; the split of the occupied sum into
+ * tiles is the band-group split of section 5, summed on the device. */
+fock_status fock_apply(const fock_cell *cell, const double q[3], int32_t dtype, const fock_orbs *occ,
+                       const fock_orbs *tgt, void *vx_out, void *ws, size_t ws_bytes, void *stream);
+
+/* Exchange energy (section 4, reciprocal-space form):
+ * *ex_out = -1/2 sum_ij f_i g_j Omega sum_G K(q+G) |rho_ij(G)|^2, with f = occ.w
+ * and g = tgt.w; ex_out is a device FP64 scalar.  Accumulated in FP64 with a
+ * fixed reduction order (bitwise reproducible run to run). */
+fock_status fock_energy(const fock_cell *cell, const double q[3], int32_t dtype, const fock_orbs *occ,
+                        const fock_orbs *tgt, double *ex_out, void *ws, size_t ws_bytes, void *stream);
+
+/* Gradient of fock_energy, scaled by the device FP64 scalar *grad_ex:
+ * grad_tgt[j] = grad_ex * dE/d conj(d_j)  =  grad_ex * 1/2 g_j (V_x psi_j)
+ * grad_occ[i] = grad_ex * dE/d conj(c_i)  =  grad_ex * 1/2 f_i (V'_x phi_i)
+ * (Wirtinger derivatives; V'_x swaps the two blocks and q -> -q).  Either
+ * output may be NULL.  Layouts as the inputs ([nb][ld]).  Pair densities are
+ * recomputed, not stored. */
+fock_status fock_energy_backward(const fock_cell *cell, const double q[3], int32_t dtype, const fock_orbs *occ,
+                                 const fock_orbs *tgt, const double *grad_ex, void *grad_occ, void *grad_tgt,
+                                 void *ws, size_t ws_bytes, void *stream);
+
+/* Auxiliary: unnormalised 3-D transform of nb boxes in place (device
+ * [nb][n1][n2][n3] complex of dtype); sign = -1 forward (sum e^{-iG.r}),
+ * +1 backward.  The same transforms the band-pair path uses; exposed so
+ * they can be checked on their own. */
+fock_status fock_fft3d(const int32_t n[3], int32_t dtype, int32_t sign, void *x, int32_t nb, void *stream);
+
+const char *fock_status_string(fock_status status);
+const char *fock_last_error(void);
+
+/* Free every cached plan (twiddle tables, sphere index tables) of this process. */
+void fock_release_plans(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FOCK_H */

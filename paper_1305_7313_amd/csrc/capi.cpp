@@ -1,0 +1,619 @@
+// C ABI of the exact-exchange path: validation, plan cache and the band-pair
+// schedule (section 4 and the band-group loop split of section 5).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/fock.h"
+#include "fock_launch.h"
+
+using namespace fockx;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+fock_status fail(fock_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+// ---------------------------------------------------------------------------
+// Plans: per device, grid, lattice, dtype and sphere.
+// ---------------------------------------------------------------------------
+struct Plan {
+  int device = 0;
+  int n[3] = {0, 0, 0};
+  long long N = 0;
+  int dtype = 0;
+  double a[3][3];
+  double b[3][3];
+  double omega = 0.0;
+  int npw = 0;
+  int* d_slot = nullptr;        // [npw] flat box index of each sphere G
+  void* d_tw[3] = {nullptr, nullptr, nullptr};  // per axis, length n_a, dtype precision
+  ~Plan() {
+    hipSetDevice(device);
+    if (d_slot) (void)hipFree(d_slot);
+    for (auto p : d_tw)
+      if (p) (void)hipFree(p);
+  }
+};
+
+using PlanKey = std::tuple<int, int, int, int, int, int, uint64_t, std::string>;
+// Heap-held and never destroyed at exit: device frees after the HIP runtime
+// has shut down are not safe.  fock_release_plans() frees them explicitly.
+std::mutex g_mutex;
+auto& g_plans = *new std::map<PlanKey, std::shared_ptr<Plan>>();
+auto& g_fft_plans = *new std::map<std::tuple<int, int, int>, std::shared_ptr<Plan>>();
+
+uint64_t fnv1a(const void* p, size_t n, uint64_t h = 1469598103934665603ull) {
+  const unsigned char* c = static_cast<const unsigned char*>(p);
+  for (size_t k = 0; k < n; ++k) {
+    h ^= c[k];
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+
+bool size_ok(int n) { return pencil_supported(n); }
+
+void reciprocal(const double a[3][3], double b[3][3], double* omega) {
+  const double det = a[0][0] * (a[1][1] * a[2][2] - a[1][2] * a[2][1]) -
+                     a[0][1] * (a[1][0] * a[2][2] - a[1][2] * a[2][0]) +
+                     a[0][2] * (a[1][0] * a[2][1] - a[1][1] * a[2][0]);
+  *omega = std::fabs(det);
+  // b_i = 2 pi (a_j x a_k) / det
+  const double s = 2.0 * kPi / det;
+  for (int i = 0; i < 3; ++i) {
+    const double* u = a[(i + 1) % 3];
+    const double* v = a[(i + 2) % 3];
+    b[i][0] = s * (u[1] * v[2] - u[2] * v[1]);
+    b[i][1] = s * (u[2] * v[0] - u[0] * v[2]);
+    b[i][2] = s * (u[0] * v[1] - u[1] * v[0]);
+  }
+}
+
+// tw[m] = exp(-2 pi i m / n), computed in FP64, rounded once for FP32.
+hipError_t upload_twiddles(int n, int dtype, void** out) {
+  const size_t bytes = (size_t)n * (dtype == FOCK_C128 ? 16 : 8);
+  hipError_t e = hipMalloc(out, bytes);
+  if (e != hipSuccess) return e;
+  std::vector<double> d(2 * n);
+  std::vector<float> f(2 * n);
+  for (int m = 0; m < n; ++m) {
+    const CosSin cs = cossin_2pi(m, n);
+    d[2 * m] = cs.c;
+    d[2 * m + 1] = -cs.s;
+    f[2 * m] = (float)cs.c;
+    f[2 * m + 1] = (float)(-cs.s);
+  }
+  return hipMemcpy(*out, dtype == FOCK_C128 ? (const void*)d.data() : (const void*)f.data(), bytes,
+                   hipMemcpyHostToDevice);
+}
+
+bool grid_supported(const int n[3]) {
+  if (!size_ok(n[0]) || !plane_supported(n[1], n[2])) return false;
+  const int cb = pencil_columns(n[0]);
+  return cb > 0 && (n[1] * n[2]) % cb == 0;
+}
+
+std::string grid_str(const int n[3]) {
+  char buf[96];
+  std::snprintf(buf, sizeof buf, "%dx%dx%d", n[0], n[1], n[2]);
+  return buf;
+}
+
+fock_status make_fft_plan(const int n[3], int dtype, std::shared_ptr<Plan>* out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(FOCK_E_HIP, "hipGetDevice failed");
+  std::lock_guard<std::mutex> lk(g_mutex);
+  auto key = std::make_tuple(dev * 4 + dtype, n[0], n[1] * 1000 + n[2]);
+  auto it = g_fft_plans.find(key);
+  if (it != g_fft_plans.end()) {
+    *out = it->second;
+    return FOCK_OK;
+  }
+  auto p = std::make_shared<Plan>();
+  p->device = dev;
+  for (int k = 0; k < 3; ++k) p->n[k] = n[k];
+  p->N = (long long)n[0] * n[1] * n[2];
+  p->dtype = dtype;
+  for (int k = 0; k < 3; ++k) {
+    hipError_t e = upload_twiddles(n[k], dtype, &p->d_tw[k]);
+    if (e != hipSuccess) return fail(FOCK_E_HIP, std::string("twiddle upload: ") + hipGetErrorString(e));
+  }
+  g_fft_plans[key] = p;
+  *out = p;
+  return FOCK_OK;
+}
+
+// Validates the cell and returns (creating if needed) its plan.
+fock_status get_plan(const fock_cell* cell, int dtype, std::shared_ptr<Plan>* out) {
+  if (!cell) return fail(FOCK_E_ARG, "cell is NULL");
+  if (dtype != FOCK_C128 && dtype != FOCK_C64) return fail(FOCK_E_ARG, "dtype must be FOCK_C128 or FOCK_C64");
+  for (int k = 0; k < 3; ++k)
+    if (cell->n[k] <= 0) return fail(FOCK_E_ARG, "grid sizes must be positive");
+  if (!grid_supported(cell->n))
+    return fail(FOCK_E_UNSUPPORTED_GRID, "no compiled transforms for grid " + grid_str(cell->n));
+  if (cell->npw <= 0 || !cell->miller) return fail(FOCK_E_ARG, "empty G-sphere (npw <= 0 or miller NULL)");
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j)
+      if (!std::isfinite(cell->a[i][j])) return fail(FOCK_E_ARG, "lattice vectors must be finite");
+  double b[3][3], omega = 0.0;
+  reciprocal(cell->a, b, &omega);
+  if (!(omega > 1e-12)) return fail(FOCK_E_ARG, "cell volume is not positive");
+  if (cell->g0 != FOCK_G0_ZERO && cell->g0 != FOCK_G0_GB) return fail(FOCK_E_ARG, "g0 must be ZERO or GB");
+  if (cell->g0 == FOCK_G0_GB) {
+    if (!(cell->gb_alpha > 0.0) || !std::isfinite(cell->gb_alpha)) return fail(FOCK_E_ARG, "gb_alpha must be > 0");
+    for (int k = 0; k < 3; ++k)
+      if (cell->nq[k] < 1) return fail(FOCK_E_ARG, "nq must be >= 1");
+  }
+  if (std::isnan(cell->ecut_fock)) return fail(FOCK_E_ARG, "ecut_fock is NaN");
+
+  int dev = 0;
+  const bool have_dev = hipGetDevice(&dev) == hipSuccess;
+  const size_t mbytes = (size_t)cell->npw * 3 * sizeof(int32_t);
+  const uint64_t h = fnv1a(cell->miller, mbytes);
+  std::string akey(reinterpret_cast<const char*>(cell->a), sizeof(cell->a));
+  PlanKey key(dev, dtype, cell->n[0], cell->n[1], cell->n[2], cell->npw, h, akey);
+  if (have_dev) {
+    std::lock_guard<std::mutex> lk(g_mutex);
+    auto it = g_plans.find(key);
+    if (it != g_plans.end()) {
+      *out = it->second;
+      return FOCK_OK;
+    }
+  }
+  // Sphere checks (host only): alias-free bound and uniqueness.
+  const long long N = (long long)cell->n[0] * cell->n[1] * cell->n[2];
+  std::vector<int> slot(cell->npw);
+  std::vector<unsigned char> seen((size_t)N, 0);
+  for (int p = 0; p < cell->npw; ++p) {
+    int idx[3];
+    for (int k = 0; k < 3; ++k) {
+      const int m = cell->miller[3 * p + k];
+      if (4 * (long long)std::abs(m) > (long long)cell->n[k] - 1) {
+        char buf[160];
+        std::snprintf(buf, sizeof buf, "Miller index %d on axis %d exceeds (n-1)/4 for n=%d (pair products would alias)",
+                      m, k, cell->n[k]);
+        return fail(FOCK_E_ALIAS, buf);
+      }
+      idx[k] = (m % cell->n[k] + cell->n[k]) % cell->n[k];
+    }
+    const long long flat = ((long long)idx[0] * cell->n[1] + idx[1]) * cell->n[2] + idx[2];
+    if (seen[flat]) return fail(FOCK_E_ALIAS, "repeated G-vector in the sphere list");
+    seen[flat] = 1;
+    slot[p] = (int)flat;
+  }
+  if (!have_dev) return fail(FOCK_E_HIP, "no HIP device available");
+  auto p = std::make_shared<Plan>();
+  p->device = dev;
+  for (int k = 0; k < 3; ++k) p->n[k] = cell->n[k];
+  p->N = N;
+  p->dtype = dtype;
+  std::memcpy(p->a, cell->a, sizeof(p->a));
+  std::memcpy(p->b, b, sizeof(b));
+  p->omega = omega;
+  p->npw = cell->npw;
+  hipError_t e = hipMalloc(&p->d_slot, sizeof(int) * (size_t)cell->npw);
+  if (e == hipSuccess) e = hipMemcpy(p->d_slot, slot.data(), sizeof(int) * (size_t)cell->npw, hipMemcpyHostToDevice);
+  for (int k = 0; k < 3 && e == hipSuccess; ++k) e = upload_twiddles(cell->n[k], dtype, &p->d_tw[k]);
+  if (e != hipSuccess) return fail(FOCK_E_HIP, std::string("plan upload: ") + hipGetErrorString(e));
+  std::lock_guard<std::mutex> lk(g_mutex);
+  g_plans[key] = p;
+  *out = p;
+  return FOCK_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Tiling and workspace layout
+// ---------------------------------------------------------------------------
+constexpr int kTileDefault = 16;
+constexpr int kGbParts = 512;
+
+struct Tiles {
+  int ti, tj;
+};
+Tiles tiles_for(int n_occ, int n_tgt) {
+  Tiles t;
+  t.ti = n_occ < kTileDefault ? (n_occ > 0 ? n_occ : 1) : kTileDefault;
+  t.tj = n_tgt < kTileDefault ? (n_tgt > 0 ? n_tgt : 1) : kTileDefault;
+  return t;
+}
+
+size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Layout {
+  size_t phiA, phiB, acc, w, epart, tile_e, k0, gbpart, total;
+};
+
+Layout layout(long long N, int cplx_bytes, int ngroups, int n_occ, int n_tgt) {
+  // Sized for both role orders (the backward pass swaps the blocks).
+  const int nmax = n_occ > n_tgt ? n_occ : n_tgt;
+  const Tiles t = tiles_for(nmax, nmax);
+  const size_t nb = (size_t)N * cplx_bytes;
+  const int nt_i = (n_occ + t.ti - 1) / t.ti, nt_j = (n_tgt + t.tj - 1) / t.tj;
+  const int ntiles = (nt_i > 0 ? nt_i : 1) * (nt_j > 0 ? nt_j : 1);
+  Layout L;
+  size_t off = 0;
+  L.phiA = off; off += align_up(nb * (size_t)nmax);
+  L.phiB = off; off += align_up(nb * (size_t)nmax);
+  L.acc = off; off += align_up(nb * (size_t)t.tj);
+  L.w = off; off += align_up(nb * (size_t)t.ti * t.tj);
+  L.epart = off; off += align_up(sizeof(double) * (size_t)t.ti * t.tj * ngroups);
+  L.tile_e = off; off += align_up(sizeof(double) * (size_t)ntiles);
+  L.k0 = off; off += align_up(sizeof(double));
+  L.gbpart = off; off += align_up(sizeof(double) * kGbParts);
+  L.total = off;
+  return L;
+}
+
+fock_status check_orbs(const fock_orbs* o, int npw, const char* name) {
+  if (!o) return fail(FOCK_E_ARG, std::string(name) + " is NULL");
+  if (o->nb < 0) return fail(FOCK_E_ARG, std::string(name) + ".nb < 0");
+  if (o->nb > 0) {
+    if (!o->c) return fail(FOCK_E_ARG, std::string(name) + ".c is NULL");
+    if (!o->w) return fail(FOCK_E_ARG, std::string(name) + ".w is NULL");
+    if (o->ld < npw) return fail(FOCK_E_ARG, std::string(name) + ".ld < npw");
+  }
+  return FOCK_OK;
+}
+
+#define FX_HIP(call)                                                                           \
+  do {                                                                                         \
+    hipError_t e_ = (call);                                                                    \
+    if (e_ != hipSuccess) return fail(FOCK_E_HIP, std::string(#call ": ") + hipGetErrorString(e_)); \
+  } while (0)
+
+template <typename T>
+struct Engine {
+  const Plan& P;
+  hipStream_t s;
+  int ngroups;
+  Engine(const Plan& p, hipStream_t st) : P(p), s(st) { ngroups = P.n[1] * P.n[2] / pencil_columns(P.n[0]); }
+
+  fock_status to_real_space(const void* c, int ld, int nb, void* box) {
+    if (nb <= 0) return FOCK_OK;
+    FX_HIP(launch_zero<T>(box, P.N * nb, s));
+    FX_HIP(launch_scatter<T>(c, ld, P.d_slot, P.npw, nb, box, P.N, s));
+    return transform(box, nb, +1);
+  }
+
+  fock_status transform(void* box, int nb, int sign) {
+    PencilArgs pa{};
+    pa.x = box;
+    pa.tw1 = P.d_tw[0];
+    pa.N = P.N;
+    pa.n2 = P.n[1];
+    pa.n3 = P.n[2];
+    pa.count = nb;
+    PlaneArgs la{};
+    la.x = box;
+    la.tw2 = P.d_tw[1];
+    la.tw3 = P.d_tw[2];
+    la.N = P.N;
+    la.n1 = P.n[0];
+    la.nb = nb;
+    if (sign > 0) {
+      FX_HIP(launch_pencil<T>(PENCIL_INV, P.n[0], pa, nb * ngroups, s));
+      FX_HIP(launch_plane<T>(PLANE_INV, P.n[1], P.n[2], la, nb * P.n[0], s));
+    } else {
+      FX_HIP(launch_plane<T>(PLANE_FWD, P.n[1], P.n[2], la, nb * P.n[0], s));
+      FX_HIP(launch_pencil<T>(PENCIL_FWD, P.n[0], pa, nb * ngroups, s));
+    }
+    return FOCK_OK;
+  }
+
+  KernelParams kparams(const double q[3], bool q_zero, const fock_cell* cell, double* d_k0) {
+    KernelParams kp{};
+    std::memcpy(kp.b, P.b, sizeof(kp.b));
+    for (int k = 0; k < 3; ++k) kp.q[k] = q[k];
+    kp.ecut = cell->ecut_fock;
+    kp.k0 = d_k0;
+    kp.q_zero = q_zero ? 1 : 0;
+    return kp;
+  }
+
+  // K at q + G = 0 into d_k0 (device FP64 scalar).
+  fock_status g0_constant(const fock_cell* cell, bool q_zero, double* d_k0, double* d_part) {
+    if (!q_zero || cell->g0 == FOCK_G0_ZERO) {
+      FX_HIP(launch_set_scalar(d_k0, 0.0, s));
+      return FOCK_OK;
+    }
+    KernelParams kp{};
+    std::memcpy(kp.b, P.b, sizeof(kp.b));
+    const int nqt = cell->nq[0] * cell->nq[1] * cell->nq[2];
+    const double head = nqt * P.omega / std::sqrt(kPi * cell->gb_alpha);
+    FX_HIP(launch_gb(kp, P.n, cell->nq, cell->gb_alpha, head, d_part, kGbParts, d_k0, s));
+    return FOCK_OK;
+  }
+
+  // The band-pair loop.  mode 0: apply -> out; mode 1: energy partials -> tile_e.
+  fock_status pairs(const fock_cell* cell, const double q[3], bool q_zero, const void* phiA, const double* fA,
+                    int nA, const void* phiB, const double* gB, int nB, char* ws, const Layout& L, bool energy,
+                    void* out, int ldo, double s0, const double* wout, const double* gscale) {
+    const Tiles t = tiles_for(nA, nB);
+    void* acc = ws + L.acc;
+    void* w = ws + L.w;
+    double* epart = reinterpret_cast<double*>(ws + L.epart);
+    double* tile_e = reinterpret_cast<double*>(ws + L.tile_e);
+    double* d_k0 = reinterpret_cast<double*>(ws + L.k0);
+    KernelParams kp = kparams(q, q_zero, cell, d_k0);
+    int tile = 0;
+    for (int j0 = 0; j0 < nB; j0 += t.tj) {
+      const int tj = (nB - j0) < t.tj ? (nB - j0) : t.tj;
+      if (!energy) FX_HIP(launch_zero<T>(acc, P.N * tj, s));
+      for (int i0 = 0; i0 < nA; i0 += t.ti, ++tile) {
+        const int ti = (nA - i0) < t.ti ? (nA - i0) : t.ti;
+        PlaneArgs la{};
+        la.a = phiA;
+        la.bsrc = phiB;
+        la.w = w;
+        la.acc = acc;
+        la.f = fA;
+        la.tw2 = P.d_tw[1];
+        la.tw3 = P.d_tw[2];
+        la.N = P.N;
+        la.i0 = i0;
+        la.j0 = j0;
+        la.ti = ti;
+        la.tj = tj;
+        la.n1 = P.n[0];
+        la.fscale = 1.0;
+        FX_HIP(launch_plane<T>(PLANE_PAIR_FWD, P.n[1], P.n[2], la, ti * tj * P.n[0], s));
+        PencilArgs pa{};
+        pa.x = w;
+        pa.epart = energy ? epart : nullptr;
+        pa.tw1 = P.d_tw[0];
+        pa.kp = kp;
+        pa.N = P.N;
+        pa.n2 = P.n[1];
+        pa.n3 = P.n[2];
+        pa.count = ti * tj;
+        if (energy) {
+          FX_HIP(launch_pencil<T>(PENCIL_FE, P.n[0], pa, ti * tj * ngroups, s));
+          // epart is laid out [ii*tj + jj][group]
+          FX_HIP(launch_energy_tile(epart, ngroups, fA, gB, i0, j0, ti, tj, nullptr, tile_e + tile, s));
+        } else {
+          FX_HIP(launch_pencil<T>(PENCIL_FKI, P.n[0], pa, ti * tj * ngroups, s));
+          FX_HIP(launch_plane<T>(PLANE_INV_MAC, P.n[1], P.n[2], la, tj * P.n[0], s));
+        }
+      }
+      if (!energy) {
+        fock_status st = transform(acc, tj, -1);
+        if (st != FOCK_OK) return st;
+        char* o = static_cast<char*>(out) + (size_t)j0 * ldo * sizeof(cx<T>);
+        FX_HIP(launch_gather<T>(acc, P.N, P.d_slot, P.npw, tj, o, ldo, s0, wout, j0, gscale, s));
+      }
+    }
+    return FOCK_OK;
+  }
+};
+
+template <typename T>
+fock_status apply_impl(const fock_cell* cell, const Plan& P, const double q[3], bool q_zero, const fock_orbs* occ,
+                       const fock_orbs* tgt, char* ws, const Layout& L, hipStream_t s, void* out, double s0,
+                       const double* wout, const double* gscale) {
+  Engine<T> E(P, s);
+  if (tgt->nb == 0) return FOCK_OK;
+  const double* d_k0 = reinterpret_cast<double*>(ws + L.k0);
+  fock_status st = E.g0_constant(cell, q_zero, const_cast<double*>(d_k0), reinterpret_cast<double*>(ws + L.gbpart));
+  if (st != FOCK_OK) return st;
+  void* phiA = ws + L.phiA;
+  void* phiB = ws + L.phiB;
+  const bool same = occ->c == tgt->c && occ->nb == tgt->nb && occ->ld == tgt->ld;
+  if ((st = E.to_real_space(occ->c, occ->ld, occ->nb, phiA)) != FOCK_OK) return st;
+  if (same) phiB = phiA;
+  else if ((st = E.to_real_space(tgt->c, tgt->ld, tgt->nb, phiB)) != FOCK_OK) return st;
+  if (occ->nb == 0) {
+    // no occupied states: V_x psi = 0 on the sphere
+    void* acc = ws + L.acc;
+    const Tiles t = tiles_for(1, tgt->nb);
+    FX_HIP(launch_zero<T>(acc, P.N * t.tj, s));
+    for (int j0 = 0; j0 < tgt->nb; j0 += t.tj) {
+      const int tj = (tgt->nb - j0) < t.tj ? (tgt->nb - j0) : t.tj;
+      char* o = static_cast<char*>(out) + (size_t)j0 * tgt->ld * sizeof(cx<T>);
+      FX_HIP(launch_gather<T>(acc, P.N, P.d_slot, P.npw, tj, o, tgt->ld, 0.0, nullptr, 0, nullptr, s));
+    }
+    return FOCK_OK;
+  }
+  return E.pairs(cell, q, q_zero, phiA, occ->w, occ->nb, phiB, tgt->w, tgt->nb, ws, L, false, out, tgt->ld, s0, wout,
+                 gscale);
+}
+
+template <typename T>
+fock_status energy_impl(const fock_cell* cell, const Plan& P, const double q[3], bool q_zero, const fock_orbs* occ,
+                        const fock_orbs* tgt, char* ws, const Layout& L, hipStream_t s, double* ex) {
+  Engine<T> E(P, s);
+  if (occ->nb == 0 || tgt->nb == 0) {
+    FX_HIP(launch_set_scalar(ex, 0.0, s));
+    return FOCK_OK;
+  }
+  double* d_k0 = reinterpret_cast<double*>(ws + L.k0);
+  fock_status st = E.g0_constant(cell, q_zero, d_k0, reinterpret_cast<double*>(ws + L.gbpart));
+  if (st != FOCK_OK) return st;
+  void* phiA = ws + L.phiA;
+  void* phiB = ws + L.phiB;
+  const bool same = occ->c == tgt->c && occ->nb == tgt->nb && occ->ld == tgt->ld;
+  if ((st = E.to_real_space(occ->c, occ->ld, occ->nb, phiA)) != FOCK_OK) return st;
+  if (same) phiB = phiA;
+  else if ((st = E.to_real_space(tgt->c, tgt->ld, tgt->nb, phiB)) != FOCK_OK) return st;
+  st = E.pairs(cell, q, q_zero, phiA, occ->w, occ->nb, phiB, tgt->w, tgt->nb, ws, L, true, nullptr, 0, 0.0, nullptr,
+               nullptr);
+  if (st != FOCK_OK) return st;
+  const Tiles t = tiles_for(occ->nb, tgt->nb);
+  const int ntiles = ((occ->nb + t.ti - 1) / t.ti) * ((tgt->nb + t.tj - 1) / t.tj);
+  const double scale = -0.5 / (P.omega * (double)P.N * (double)P.N);
+  FX_HIP(launch_energy_final(reinterpret_cast<double*>(ws + L.tile_e), ntiles, scale, ex, s));
+  return FOCK_OK;
+}
+
+struct Prepared {
+  std::shared_ptr<Plan> plan;
+  Layout L;
+  bool q_zero = false;
+};
+
+fock_status check_cell_host(const fock_cell* cell, int dtype) {
+  if (!cell) return fail(FOCK_E_ARG, "cell is NULL");
+  if (dtype != FOCK_C128 && dtype != FOCK_C64) return fail(FOCK_E_ARG, "dtype must be FOCK_C128 or FOCK_C64");
+  for (int k = 0; k < 3; ++k)
+    if (cell->n[k] <= 0) return fail(FOCK_E_ARG, "grid sizes must be positive");
+  if (cell->npw <= 0 || !cell->miller) return fail(FOCK_E_ARG, "empty G-sphere (npw <= 0 or miller NULL)");
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j)
+      if (!std::isfinite(cell->a[i][j])) return fail(FOCK_E_ARG, "lattice vectors must be finite");
+  return FOCK_OK;
+}
+
+// q + G = 0 for a non-zero q means q is a reciprocal-lattice vector:
+// its fractional coordinates a_a . q / (2 pi) are all integers.
+fock_status check_q(const fock_cell* cell, const double q[3], bool* q_zero) {
+  if (!q) return fail(FOCK_E_ARG, "q is NULL");
+  for (int k = 0; k < 3; ++k)
+    if (!std::isfinite(q[k])) return fail(FOCK_E_ARG, "q must be finite");
+  *q_zero = q[0] == 0.0 && q[1] == 0.0 && q[2] == 0.0;
+  if (!*q_zero) {
+    bool all_int = true;
+    for (int k = 0; k < 3; ++k) {
+      const double s = (cell->a[k][0] * q[0] + cell->a[k][1] * q[1] + cell->a[k][2] * q[2]) / (2.0 * kPi);
+      if (std::fabs(s - std::nearbyint(s)) > 1e-9) all_int = false;
+    }
+    if (all_int) return fail(FOCK_E_SINGULAR_Q, "q is a non-zero reciprocal-lattice vector: fold it into the zone");
+  }
+  return FOCK_OK;
+}
+
+fock_status prepare(const fock_cell* cell, const double q[3], int dtype, const fock_orbs* occ, const fock_orbs* tgt,
+                    void* ws, size_t ws_bytes, Prepared* out) {
+  fock_status st = check_cell_host(cell, dtype);
+  if (st != FOCK_OK) return st;
+  if (!grid_supported(cell->n))
+    return fail(FOCK_E_UNSUPPORTED_GRID, "no compiled transforms for grid " + grid_str(cell->n));
+  if ((st = check_orbs(occ, cell->npw, "occ")) != FOCK_OK) return st;
+  if ((st = check_orbs(tgt, cell->npw, "tgt")) != FOCK_OK) return st;
+  if ((st = check_q(cell, q, &out->q_zero)) != FOCK_OK) return st;
+  const long long N = (long long)cell->n[0] * cell->n[1] * cell->n[2];
+  const int ngroups = cell->n[1] * cell->n[2] / pencil_columns(cell->n[0]);
+  out->L = layout(N, dtype == FOCK_C128 ? 16 : 8, ngroups, occ->nb, tgt->nb);
+  if (!ws || ws_bytes < out->L.total) {
+    char buf[160];
+    std::snprintf(buf, sizeof buf, "workspace of %zu bytes is smaller than the %zu needed", ws_bytes, out->L.total);
+    return fail(FOCK_E_WORKSPACE, buf);
+  }
+  return get_plan(cell, dtype, &out->plan);
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t fock_workspace_size(const fock_cell* cell, int32_t dtype, int32_t n_occ, int32_t n_tgt) {
+  if (!cell || n_occ < 0 || n_tgt < 0 || (dtype != FOCK_C128 && dtype != FOCK_C64)) return 0;
+  if (!grid_supported(cell->n)) return 0;
+  const long long N = (long long)cell->n[0] * cell->n[1] * cell->n[2];
+  const int ngroups = cell->n[1] * cell->n[2] / pencil_columns(cell->n[0]);
+  return layout(N, dtype == FOCK_C128 ? 16 : 8, ngroups, n_occ, n_tgt).total;
+}
+
+fock_status fock_apply(const fock_cell* cell, const double q[3], int32_t dtype, const fock_orbs* occ,
+                       const fock_orbs* tgt, void* vx_out, void* ws, size_t ws_bytes, void* stream) {
+  Prepared pr;
+  fock_status st = prepare(cell, q, dtype, occ, tgt, ws, ws_bytes, &pr);
+  if (st != FOCK_OK) return st;
+  if (tgt->nb > 0 && !vx_out) return fail(FOCK_E_ARG, "vx_out is NULL");
+  const Plan& P = *pr.plan;
+  const double s0 = -1.0 / (P.omega * (double)P.N * (double)P.N);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  char* w = static_cast<char*>(ws);
+  if (dtype == FOCK_C128)
+    return apply_impl<double>(cell, P, q, pr.q_zero, occ, tgt, w, pr.L, s, vx_out, s0, nullptr, nullptr);
+  return apply_impl<float>(cell, P, q, pr.q_zero, occ, tgt, w, pr.L, s, vx_out, s0, nullptr, nullptr);
+}
+
+fock_status fock_energy(const fock_cell* cell, const double q[3], int32_t dtype, const fock_orbs* occ,
+                        const fock_orbs* tgt, double* ex_out, void* ws, size_t ws_bytes, void* stream) {
+  Prepared pr;
+  fock_status st = prepare(cell, q, dtype, occ, tgt, ws, ws_bytes, &pr);
+  if (st != FOCK_OK) return st;
+  if (!ex_out) return fail(FOCK_E_ARG, "ex_out is NULL");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  char* w = static_cast<char*>(ws);
+  if (dtype == FOCK_C128) return energy_impl<double>(cell, *pr.plan, q, pr.q_zero, occ, tgt, w, pr.L, s, ex_out);
+  return energy_impl<float>(cell, *pr.plan, q, pr.q_zero, occ, tgt, w, pr.L, s, ex_out);
+}
+
+fock_status fock_energy_backward(const fock_cell* cell, const double q[3], int32_t dtype, const fock_orbs* occ,
+                                 const fock_orbs* tgt, const double* grad_ex, void* grad_occ, void* grad_tgt,
+                                 void* ws, size_t ws_bytes, void* stream) {
+  Prepared pr;
+  fock_status st = prepare(cell, q, dtype, occ, tgt, ws, ws_bytes, &pr);
+  if (st != FOCK_OK) return st;
+  if (!grad_ex) return fail(FOCK_E_ARG, "grad_ex is NULL");
+  const Plan& P = *pr.plan;
+  const double s0 = -0.5 / (P.omega * (double)P.N * (double)P.N);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  char* w = static_cast<char*>(ws);
+  if (grad_tgt) {
+    // dE/d conj(d_j) = 1/2 g_j (V_x psi_j)
+    st = dtype == FOCK_C128 ? apply_impl<double>(cell, P, q, pr.q_zero, occ, tgt, w, pr.L, s, grad_tgt, s0, tgt->w, grad_ex)
+                            : apply_impl<float>(cell, P, q, pr.q_zero, occ, tgt, w, pr.L, s, grad_tgt, s0, tgt->w, grad_ex);
+    if (st != FOCK_OK) return st;
+  }
+  if (grad_occ) {
+    // dE/d conj(c_i) = 1/2 f_i (V'_x phi_i): targets act as occupied (weights g), q -> -q
+    const double mq[3] = {-q[0], -q[1], -q[2]};
+    st = dtype == FOCK_C128 ? apply_impl<double>(cell, P, mq, pr.q_zero, tgt, occ, w, pr.L, s, grad_occ, s0, occ->w, grad_ex)
+                            : apply_impl<float>(cell, P, mq, pr.q_zero, tgt, occ, w, pr.L, s, grad_occ, s0, occ->w, grad_ex);
+    if (st != FOCK_OK) return st;
+  }
+  return FOCK_OK;
+}
+
+fock_status fock_fft3d(const int32_t n[3], int32_t dtype, int32_t sign, void* x, int32_t nb, void* stream) {
+  if (!n) return fail(FOCK_E_ARG, "n is NULL");
+  if (dtype != FOCK_C128 && dtype != FOCK_C64) return fail(FOCK_E_ARG, "bad dtype");
+  if (sign != 1 && sign != -1) return fail(FOCK_E_ARG, "sign must be +1 or -1");
+  if (nb < 0) return fail(FOCK_E_ARG, "nb < 0");
+  if (nb > 0 && !x) return fail(FOCK_E_ARG, "x is NULL");
+  int nn[3] = {n[0], n[1], n[2]};
+  if (!grid_supported(nn)) return fail(FOCK_E_UNSUPPORTED_GRID, "no compiled transforms for grid " + grid_str(nn));
+  std::shared_ptr<Plan> p;
+  fock_status st = make_fft_plan(nn, dtype, &p);
+  if (st != FOCK_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (dtype == FOCK_C128) return Engine<double>(*p, s).transform(x, nb, sign);
+  return Engine<float>(*p, s).transform(x, nb, sign);
+}
+
+const char* fock_status_string(fock_status st) {
+  switch (st) {
+    case FOCK_OK: return "ok";
+    case FOCK_E_ARG: return "invalid argument";
+    case FOCK_E_ALIAS: return "G-sphere does not fit the grid without aliasing";
+    case FOCK_E_SINGULAR_Q: return "q + G = 0 for a non-zero q";
+    case FOCK_E_WORKSPACE: return "workspace too small";
+    case FOCK_E_UNSUPPORTED_GRID: return "unsupported FFT grid";
+    case FOCK_E_HIP: return "HIP runtime error";
+  }
+  return "unknown status";
+}
+
+const char* fock_last_error(void) { return g_last_error.c_str(); }
+
+void fock_release_plans(void) {
+  std::lock_guard<std::mutex> lk(g_mutex);
+  g_plans.clear();
+  g_fft_plans.clear();
+}
+
+}  // extern "C"

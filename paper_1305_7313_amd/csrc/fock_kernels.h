@@ -1,0 +1,359 @@
+// Device kernels of the exact-exchange band-pair path (section 4 of Varini et
+// al., "Enhancement of DFT-calculations at Petascale"):
+//
+//   a1  orbitals to real space:  scatter the sphere, backward 3-D FFT
+//   P1  pair density conj(phi_i) psi_j  +  forward FFT over the plane axes
+//   P2  forward FFT along axis 1, Coulomb kernel K(q+G) (+ FP64 energy
+//       partials), backward FFT along axis 1
+//   P3  backward FFT over the plane axes, multiply by f_i phi_i, accumulate
+//       over the occupied tile into (V_x psi)_j in real space
+//   a7  per target: forward 3-D FFT, gather the sphere, scale
+//
+// The FFT box is C order [n1][n2][n3]; a "plane" is one i1 slice (n2*n3
+// contiguous values), a "pencil" runs along i1 with stride n2*n3.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <utility>
+
+#include "fft_engine.h"
+
+namespace fockx {
+
+constexpr double kFourPi = 12.566370614359172953850573533118011536788677597500;
+
+enum PlaneMode : int {
+  PLANE_PAIR_FWD = 0,  // P1
+  PLANE_INV_MAC = 1,   // P3
+  PLANE_FWD = 2,       // in place, forward (a7)
+  PLANE_INV = 3,       // in place, backward (a1)
+};
+enum PencilMode : int {
+  PENCIL_FKI = 0,  // P2: forward, kernel, backward (+ optional energy partials)
+  PENCIL_FE = 1,   // forward + energy partials only
+  PENCIL_FWD = 2,  // in place, forward (a7)
+  PENCIL_INV = 3,  // in place, backward (a1)
+};
+
+// What the kernel needs to evaluate K(q+G) at G = m1 b1 + m2 b2 + m3 b3.
+struct KernelParams {
+  double b[3][3];      // reciprocal lattice vectors (rows), bohr^-1
+  double q[3];         // bohr^-1
+  double ecut;         // cutoff on |q+G|^2; <= 0: none
+  const double* k0;    // device scalar: K at q+G = 0 (only used when q_zero)
+  int q_zero;
+};
+
+struct PlaneArgs {
+  void* x;             // in-place modes: [nb][N]
+  const void* a;       // occupied orbitals in real space [*][N]
+  const void* bsrc;    // target orbitals in real space [*][N]
+  void* w;             // pair buffer [ti*tj][N], slot = ii*tj + jj
+  void* acc;           // accumulators [tj][N]
+  const double* f;     // occupied weights, absolute index
+  const void* tw2;     // twiddle table, length n2
+  const void* tw3;     // twiddle table, length n3
+  long long N;
+  int i0, j0, ti, tj;  // tile origin and extent
+  int n1, nb;
+  double fscale;       // constant factor on f in P3
+};
+
+struct PencilArgs {
+  void* x;             // [npairs or nb][N]
+  double* epart;       // energy partials [npairs][ngroups] or null
+  const void* tw1;     // twiddle table, length n1
+  KernelParams kp;
+  long long N;
+  int n2, n3, count;   // count = pairs or orbitals
+};
+
+// Hardware dispatches workgroup w to XCD (w mod 8).  Renumber so that
+// consecutive logical blocks run on the same XCD and share its L2.
+__device__ __forceinline__ int xcd_logical(int w, int G) {
+  const int x = w & 7, slot = w >> 3;
+  const int per = G >> 3, extra = G & 7;
+  return x * per + (x < extra ? x : extra) + slot;
+}
+
+template <typename T>
+__device__ __forceinline__ void load_table(cx<T>* dst, const void* src, int n) {
+  const cx<T>* s = reinterpret_cast<const cx<T>*>(src);
+  for (int k = threadIdx.x; k < n; k += blockDim.x) dst[k] = s[k];
+}
+
+__device__ __forceinline__ double block_sum(double v, double* red) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) {
+    const int nw = (blockDim.x + 63) >> 6;
+    for (int k = 0; k < nw; ++k) s += red[k];
+  }
+  return s;
+}
+
+__device__ __forceinline__ int signed_index(int i, int n) { return i < (n >> 1) ? i : i - n; }
+
+// ---------------------------------------------------------------------------
+// Plane kernel: 2-D FFT over (i2, i3) of one i1 plane.
+// ---------------------------------------------------------------------------
+template <int N2, int N3> struct PlaneShape;
+template <> struct PlaneShape<24, 24> { static constexpr int W = 128; };
+template <> struct PlaneShape<48, 48> { static constexpr int W = 256; };
+template <> struct PlaneShape<48, 64> { static constexpr int W = 128; };
+template <> struct PlaneShape<64, 64> { static constexpr int W = 256; };
+template <> struct PlaneShape<72, 72> { static constexpr int W = 576; };
+template <> struct PlaneShape<96, 96> { static constexpr int W = 384; };
+template <> struct PlaneShape<96, 128> { static constexpr int W = 512; };
+
+template <typename T, int N2, int N3> struct PlaneCfg {
+  static constexpr int W = PlaneShape<N2, N3>::W;
+  static constexpr int PLANE = N2 * N3;
+  // FP64 tiles above 64 KB exchange real and imaginary parts separately.
+  static constexpr bool SPLIT = sizeof(T) == 8 && lds_slots(PLANE) * 16 > 65536;
+  static constexpr int XBYTES = lds_slots(PLANE) * (SPLIT ? (int)sizeof(T) : 2 * (int)sizeof(T));
+  using Rw = Axis<N3, N2, true, W>;   // transforms along i3, one per row
+  using Cl = Axis<N2, N3, false, W>;  // transforms along i2, one per column
+  static constexpr int NV = Rw::NV > Cl::NV ? Rw::NV : Cl::NV;
+};
+
+template <typename T, int N2, int N3, int MODE>
+__global__ __launch_bounds__((PlaneCfg<T, N2, N3>::W)) void plane_kernel(PlaneArgs A) {
+  using Cfg = PlaneCfg<T, N2, N3>;
+  using Rw = typename Cfg::Rw;
+  using Cl = typename Cfg::Cl;
+  constexpr bool SPLIT = Cfg::SPLIT;
+  constexpr int PLANE = Cfg::PLANE;
+  __shared__ __align__(16) unsigned char smem[Cfg::XBYTES];
+  __shared__ cx<T> tw2[N2];
+  __shared__ cx<T> tw3[N3];
+  load_table<T>(tw2, A.tw2, N2);
+  load_table<T>(tw3, A.tw3, N3);
+  __syncthreads();
+
+  const int t = threadIdx.x;
+  const int lid = xcd_logical(blockIdx.x, gridDim.x);
+  const long long N = A.N;
+  cx<T> v[Cfg::NV];
+
+  if constexpr (MODE == PLANE_PAIR_FWD) {
+    const int tt = A.ti * A.tj;
+    const int i1 = lid / tt, rem = lid - i1 * tt;
+    const int ii = rem / A.tj, jj = rem - ii * A.tj;
+    const cx<T>* pa = reinterpret_cast<const cx<T>*>(A.a) + (long long)(A.i0 + ii) * N + (long long)i1 * PLANE;
+    const cx<T>* pb = reinterpret_cast<const cx<T>*>(A.bsrc) + (long long)(A.j0 + jj) * N + (long long)i1 * PLANE;
+    for_inputs<typename Rw::P0>(t, [&](int e, int b, int x) {
+      const int p = Rw::P0::pos(b, x);
+      v[e] = cmulc<T>(pa[p], pb[p]);
+    });
+    pass_compute<typename Rw::P0, -1, T>(v, tw3, t);
+    exchange<typename Rw::P0, typename Rw::P1, SPLIT, T>(v, smem, t);
+    pass_compute<typename Rw::P1, -1, T>(v, tw3, t);
+    exchange<typename Rw::P1, typename Cl::P0, SPLIT, T>(v, smem, t);
+    pass_compute<typename Cl::P0, -1, T>(v, tw2, t);
+    exchange<typename Cl::P0, typename Cl::P1, SPLIT, T>(v, smem, t);
+    pass_compute<typename Cl::P1, -1, T>(v, tw2, t);
+    cx<T>* pw = reinterpret_cast<cx<T>*>(A.w) + (long long)(ii * A.tj + jj) * N + (long long)i1 * PLANE;
+    for_outputs<typename Cl::P1>(t, [&](int e, int b, int x) { pw[Cl::P1::pos(b, x)] = v[e]; });
+  } else if constexpr (MODE == PLANE_INV_MAC) {
+    const int i1 = lid / A.tj, jj = lid - (lid / A.tj) * A.tj;
+    cx<T> s[Rw::P1::NV];
+#pragma unroll
+    for (int e = 0; e < Rw::P1::NV; ++e) s[e] = mk<T>(T(0), T(0));
+    for (int ii = 0; ii < A.ti; ++ii) {
+      const cx<T>* pw = reinterpret_cast<const cx<T>*>(A.w) + (long long)(ii * A.tj + jj) * N + (long long)i1 * PLANE;
+      for_inputs<typename Cl::P0>(t, [&](int e, int b, int x) { v[e] = pw[Cl::P0::pos(b, x)]; });
+      pass_compute<typename Cl::P0, +1, T>(v, tw2, t);
+      exchange<typename Cl::P0, typename Cl::P1, SPLIT, T>(v, smem, t);
+      pass_compute<typename Cl::P1, +1, T>(v, tw2, t);
+      exchange<typename Cl::P1, typename Rw::P0, SPLIT, T>(v, smem, t);
+      pass_compute<typename Rw::P0, +1, T>(v, tw3, t);
+      exchange<typename Rw::P0, typename Rw::P1, SPLIT, T>(v, smem, t);
+      pass_compute<typename Rw::P1, +1, T>(v, tw3, t);
+      const T fi = T(A.f[A.i0 + ii] * A.fscale);
+      const cx<T>* pa = reinterpret_cast<const cx<T>*>(A.a) + (long long)(A.i0 + ii) * N + (long long)i1 * PLANE;
+      for_outputs<typename Rw::P1>(t, [&](int e, int b, int x) {
+        const cx<T> pr = cmul<T>(pa[Rw::P1::pos(b, x)], v[e]);
+        s[e] = mk<T>(s[e].x + fi * pr.x, s[e].y + fi * pr.y);
+      });
+    }
+    cx<T>* pc = reinterpret_cast<cx<T>*>(A.acc) + (long long)jj * N + (long long)i1 * PLANE;
+    for_outputs<typename Rw::P1>(t, [&](int e, int b, int x) {
+      const int p = Rw::P1::pos(b, x);
+      pc[p] = cadd<T>(pc[p], s[e]);
+    });
+  } else if constexpr (MODE == PLANE_FWD) {
+    const int ob = lid / A.n1, i1 = lid - (lid / A.n1) * A.n1;
+    cx<T>* px = reinterpret_cast<cx<T>*>(A.x) + (long long)ob * N + (long long)i1 * PLANE;
+    for_inputs<typename Rw::P0>(t, [&](int e, int b, int x) { v[e] = px[Rw::P0::pos(b, x)]; });
+    pass_compute<typename Rw::P0, -1, T>(v, tw3, t);
+    exchange<typename Rw::P0, typename Rw::P1, SPLIT, T>(v, smem, t);
+    pass_compute<typename Rw::P1, -1, T>(v, tw3, t);
+    exchange<typename Rw::P1, typename Cl::P0, SPLIT, T>(v, smem, t);
+    pass_compute<typename Cl::P0, -1, T>(v, tw2, t);
+    exchange<typename Cl::P0, typename Cl::P1, SPLIT, T>(v, smem, t);
+    pass_compute<typename Cl::P1, -1, T>(v, tw2, t);
+    for_outputs<typename Cl::P1>(t, [&](int e, int b, int x) { px[Cl::P1::pos(b, x)] = v[e]; });
+  } else {  // PLANE_INV
+    const int ob = lid / A.n1, i1 = lid - (lid / A.n1) * A.n1;
+    cx<T>* px = reinterpret_cast<cx<T>*>(A.x) + (long long)ob * N + (long long)i1 * PLANE;
+    for_inputs<typename Cl::P0>(t, [&](int e, int b, int x) { v[e] = px[Cl::P0::pos(b, x)]; });
+    pass_compute<typename Cl::P0, +1, T>(v, tw2, t);
+    exchange<typename Cl::P0, typename Cl::P1, SPLIT, T>(v, smem, t);
+    pass_compute<typename Cl::P1, +1, T>(v, tw2, t);
+    exchange<typename Cl::P1, typename Rw::P0, SPLIT, T>(v, smem, t);
+    pass_compute<typename Rw::P0, +1, T>(v, tw3, t);
+    exchange<typename Rw::P0, typename Rw::P1, SPLIT, T>(v, smem, t);
+    pass_compute<typename Rw::P1, +1, T>(v, tw3, t);
+    for_outputs<typename Rw::P1>(t, [&](int e, int b, int x) { px[Rw::P1::pos(b, x)] = v[e]; });
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Pencil kernel: 1-D FFT along i1 for CB consecutive plane positions.
+// ---------------------------------------------------------------------------
+template <int N1> struct PencilShape;
+template <> struct PencilShape<24> { static constexpr int CB = 64, W = 128; };
+template <> struct PencilShape<48> { static constexpr int CB = 64, W = 128; };
+template <> struct PencilShape<64> { static constexpr int CB = 32, W = 256; };
+template <> struct PencilShape<72> { static constexpr int CB = 32, W = 256; };
+template <> struct PencilShape<96> { static constexpr int CB = 32, W = 128; };
+template <> struct PencilShape<128> { static constexpr int CB = 32, W = 256; };
+
+template <typename T, int N1> struct PencilCfg {
+  static constexpr int CB = PencilShape<N1>::CB;
+  static constexpr int W = PencilShape<N1>::W;
+  static constexpr int TILE = N1 * CB;
+  static constexpr bool SPLIT = sizeof(T) == 8 && lds_slots(TILE) * 16 > 65536;
+  static constexpr int XBYTES = lds_slots(TILE) * (SPLIT ? (int)sizeof(T) : 2 * (int)sizeof(T));
+  using Ax = Axis<N1, CB, false, W>;
+  static constexpr int NV = Ax::NV;
+};
+
+template <typename T, int N1, int MODE>
+__global__ __launch_bounds__((PencilCfg<T, N1>::W)) void pencil_kernel(PencilArgs A) {
+  using Cfg = PencilCfg<T, N1>;
+  using P0 = typename Cfg::Ax::P0;
+  using P1 = typename Cfg::Ax::P1;
+  constexpr bool SPLIT = Cfg::SPLIT;
+  constexpr int CB = Cfg::CB;
+  __shared__ __align__(16) unsigned char smem[Cfg::XBYTES];
+  __shared__ cx<T> tw1[N1];
+  __shared__ double red[(Cfg::W + 63) / 64];
+  load_table<T>(tw1, A.tw1, N1);
+  __syncthreads();
+
+  const int t = threadIdx.x;
+  const int plane = A.n2 * A.n3;
+  const int ngroups = plane / CB;
+  const int lid = xcd_logical(blockIdx.x, gridDim.x);
+  const int pr = lid / ngroups, g = lid - (lid / ngroups) * ngroups;
+  const int c0 = g * CB;
+  cx<T>* base = reinterpret_cast<cx<T>*>(A.x) + (long long)pr * A.N + c0;
+  cx<T> v[Cfg::NV];
+
+  constexpr int DIR0 = (MODE == PENCIL_INV) ? +1 : -1;
+  for_inputs<P0>(t, [&](int e, int b, int x) { v[e] = base[(long long)x * plane + b]; });
+  pass_compute<P0, DIR0, T>(v, tw1, t);
+  exchange<P0, P1, SPLIT, T>(v, smem, t);
+  pass_compute<P1, DIR0, T>(v, tw1, t);
+
+  if constexpr (MODE == PENCIL_FWD || MODE == PENCIL_INV) {
+    for_outputs<P1>(t, [&](int e, int b, int x) { base[(long long)x * plane + b] = v[e]; });
+    return;
+  } else {
+    // Coulomb kernel on the natural-order outputs (b = column, x = k1).
+    const KernelParams& kp = A.kp;
+    double esum = 0.0;
+    const double k0 = kp.q_zero ? *kp.k0 : 0.0;
+#pragma unroll
+    for (int s = 0; s < P1::NS; ++s) {
+      int b, i;
+      const bool act = P1::get(t, s, b, i);
+      const int c = c0 + b;
+      const int m2 = signed_index(c / A.n3, A.n2);
+      const int m3 = signed_index(c - (c / A.n3) * A.n3, A.n3);
+      const double gx = kp.q[0] + m2 * kp.b[1][0] + m3 * kp.b[2][0];
+      const double gy = kp.q[1] + m2 * kp.b[1][1] + m3 * kp.b[2][1];
+      const double gz = kp.q[2] + m2 * kp.b[1][2] + m3 * kp.b[2][2];
+#pragma unroll
+      for (int r = 0; r < P1::R; ++r) {
+        const int m1 = signed_index(P1::out_x(i, r), N1);
+        T kv;
+        if constexpr (sizeof(T) == 8) {
+          const double x0 = gx + m1 * kp.b[0][0], y0 = gy + m1 * kp.b[0][1], z0 = gz + m1 * kp.b[0][2];
+          const double g2 = x0 * x0 + y0 * y0 + z0 * z0;
+          double kk = kFourPi / g2;
+          if (kp.ecut > 0.0 && g2 > kp.ecut) kk = 0.0;
+          if (kp.q_zero && m1 == 0 && m2 == 0 && m3 == 0) kk = k0;
+          kv = kk;
+        } else {
+          const float x0 = float(gx) + float(m1) * float(kp.b[0][0]);
+          const float y0 = float(gy) + float(m1) * float(kp.b[0][1]);
+          const float z0 = float(gz) + float(m1) * float(kp.b[0][2]);
+          const float g2 = x0 * x0 + y0 * y0 + z0 * z0;
+          float kk = float(kFourPi) / g2;
+          if (kp.ecut > 0.0) {
+            const double dx = gx + m1 * kp.b[0][0], dy = gy + m1 * kp.b[0][1], dz = gz + m1 * kp.b[0][2];
+            if (dx * dx + dy * dy + dz * dz > kp.ecut) kk = 0.0f;
+          }
+          if (kp.q_zero && m1 == 0 && m2 == 0 && m3 == 0) kk = float(k0);
+          kv = kk;
+        }
+        cx<T>& z = v[s * P1::R + r];
+        if (act) esum += double(kv * (z.x * z.x + z.y * z.y));
+        z = cscale<T>(z, kv);
+      }
+    }
+    if (A.epart) {
+      const double tot = block_sum(esum, red);
+      if (t == 0) A.epart[(long long)pr * ngroups + g] = tot;
+    }
+    if constexpr (MODE == PENCIL_FKI) {
+      exchange<P1, P0, SPLIT, T>(v, smem, t);
+      pass_compute<P0, +1, T>(v, tw1, t);
+      exchange<P0, P1, SPLIT, T>(v, smem, t);
+      pass_compute<P1, +1, T>(v, tw1, t);
+      for_outputs<P1>(t, [&](int e, int b, int x) { base[(long long)x * plane + b] = v[e]; });
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Small kernels
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void zero_kernel(cx<T>* p, long long n) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride) p[k] = mk<T>(T(0), T(0));
+}
+
+// box[b][slot[p]] = c[b][p]  (box already zero)
+template <typename T>
+__global__ void scatter_kernel(const cx<T>* __restrict__ c, int ldc, const int* __restrict__ slot, int npw,
+                               cx<T>* __restrict__ box, long long N) {
+  const int b = blockIdx.y;
+  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < npw; p += gridDim.x * blockDim.x)
+    box[(long long)b * N + slot[p]] = c[(long long)b * ldc + p];
+}
+
+// out[j][p] = s0 * (w ? w[j0+j] : 1) * (g ? *g : 1) * box[j][slot[p]]
+template <typename T>
+__global__ void gather_kernel(const cx<T>* __restrict__ box, long long N, const int* __restrict__ slot, int npw,
+                              cx<T>* __restrict__ out, int ldo, double s0, const double* __restrict__ w, int j0,
+                              const double* __restrict__ g) {
+  const int j = blockIdx.y;
+  double s = s0;
+  if (w) s *= w[j0 + j];
+  if (g) s *= *g;
+  const T st = T(s);
+  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < npw; p += gridDim.x * blockDim.x)
+    out[(long long)j * ldo + p] = cscale<T>(box[(long long)j * N + slot[p]], st);
+}
+
+}  // namespace fockx

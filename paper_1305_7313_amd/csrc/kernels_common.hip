@@ -1,0 +1,120 @@
+// Type-independent kernels: energy reductions, Gygi-Baldereschi constant.
+#include "fock_launch.h"
+
+namespace fockx {
+
+// Per tile: sum_{pairs} f_i g_j sum_groups epart -> tile_e[tile]   (one block, fixed order)
+__global__ void energy_tile_kernel(const double* __restrict__ epart, int ngroups, const double* __restrict__ f,
+                                   const double* __restrict__ g, int i0, int j0, int ti, int tj,
+                                   const unsigned char* __restrict__ pair_mask, double* __restrict__ tile_e) {
+  __shared__ double red[16];
+  double acc = 0.0;
+  for (int pr = threadIdx.x; pr < ti * tj; pr += blockDim.x) {
+    const int ii = pr / tj, jj = pr - (pr / tj) * tj;
+    double s = 0.0;
+    const double* e = epart + (long long)pr * ngroups;
+    for (int k = 0; k < ngroups; ++k) s += e[k];
+    double wgt = f[i0 + ii] * g[j0 + jj];
+    if (pair_mask) wgt *= double(pair_mask[pr]);
+    acc += wgt * s;
+  }
+  const double tot = block_sum(acc, red);
+  if (threadIdx.x == 0) *tile_e = tot;
+}
+
+// ex = scale * sum_t tile_e[t]   (one thread, fixed order)
+__global__ void energy_final_kernel(const double* __restrict__ tile_e, int ntiles, double scale, double* ex) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    double s = 0.0;
+    for (int k = 0; k < ntiles; ++k) s += tile_e[k];
+    *ex = scale * s;
+  }
+}
+
+// Gygi-Baldereschi lattice sum: partial[block] = sum over (q in mesh, G in box, q+G != 0)
+// of 4 pi exp(-alpha |q+G|^2) / |q+G|^2.
+__global__ void gb_partial_kernel(KernelParams kp, int n1, int n2, int n3, int nq1, int nq2, int nq3, double alpha,
+                                  double* partial) {
+  __shared__ double red[16];
+  const long long N = (long long)n1 * n2 * n3;
+  const long long total = N * nq1 * nq2 * nq3;
+  double acc = 0.0;
+  for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < total;
+       k += (long long)gridDim.x * blockDim.x) {
+    const long long iq = k / N, ib = k - (k / N) * N;
+    const int s3 = (int)(iq % nq3), s2 = (int)((iq / nq3) % nq2), s1 = (int)(iq / ((long long)nq3 * nq2));
+    const int i3 = (int)(ib % n3), i2 = (int)((ib / n3) % n2), i1 = (int)(ib / ((long long)n3 * n2));
+    const double f1 = signed_index(i1, n1) + double(s1) / nq1;
+    const double f2 = signed_index(i2, n2) + double(s2) / nq2;
+    const double f3 = signed_index(i3, n3) + double(s3) / nq3;
+    const double gx = f1 * kp.b[0][0] + f2 * kp.b[1][0] + f3 * kp.b[2][0];
+    const double gy = f1 * kp.b[0][1] + f2 * kp.b[1][1] + f3 * kp.b[2][1];
+    const double gz = f1 * kp.b[0][2] + f2 * kp.b[1][2] + f3 * kp.b[2][2];
+    const double g2 = gx * gx + gy * gy + gz * gz;
+    if (iq == 0 && ib == 0) continue;
+    acc += kFourPi * exp(-alpha * g2) / g2;
+  }
+  const double tot = block_sum(acc, red);
+  if (threadIdx.x == 0) partial[blockIdx.x] = tot;
+}
+
+__global__ void gb_final_kernel(const double* partial, int nparts, double head, double* k0) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    double s = 0.0;
+    for (int k = 0; k < nparts; ++k) s += partial[k];
+    *k0 = head - s;
+  }
+}
+
+__global__ void set_scalar_kernel(double* p, double v) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
+}
+
+
+bool plane_supported(int n2, int n3) {
+  return (n2 == 24 && n3 == 24) || (n2 == 48 && n3 == 48) || (n2 == 48 && n3 == 64) || (n2 == 64 && n3 == 64) ||
+         (n2 == 72 && n3 == 72) || (n2 == 96 && n3 == 96) || (n2 == 96 && n3 == 128);
+}
+bool pencil_supported(int n1) {
+  return n1 == 24 || n1 == 48 || n1 == 64 || n1 == 72 || n1 == 96 || n1 == 128;
+}
+int pencil_columns(int n1) {
+  switch (n1) {
+    case 24: return PencilShape<24>::CB;
+    case 48: return PencilShape<48>::CB;
+    case 64: return PencilShape<64>::CB;
+    case 72: return PencilShape<72>::CB;
+    case 96: return PencilShape<96>::CB;
+    case 128: return PencilShape<128>::CB;
+  }
+  return 0;
+}
+
+hipError_t launch_energy_tile(const double* epart, int ngroups, const double* f, const double* g, int i0, int j0,
+                              int ti, int tj, const unsigned char* mask, double* tile_e, hipStream_t s) {
+  hipLaunchKernelGGL(energy_tile_kernel, dim3(1), dim3(256), 0, s, epart, ngroups, f, g, i0, j0, ti, tj, mask,
+                     tile_e);
+  return hipGetLastError();
+}
+
+hipError_t launch_energy_final(const double* tile_e, int ntiles, double scale, double* ex, hipStream_t s) {
+  hipLaunchKernelGGL(energy_final_kernel, dim3(1), dim3(64), 0, s, tile_e, ntiles, scale, ex);
+  return hipGetLastError();
+}
+
+hipError_t launch_gb(const KernelParams& kp, const int n[3], const int nq[3], double alpha, double head,
+                     double* partial, int nparts, double* k0, hipStream_t s) {
+  hipLaunchKernelGGL(gb_partial_kernel, dim3(nparts), dim3(256), 0, s, kp, n[0], n[1], n[2], nq[0], nq[1], nq[2],
+                     alpha, partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(gb_final_kernel, dim3(1), dim3(64), 0, s, partial, nparts, head, k0);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_scalar(double* p, double v, hipStream_t s) {
+  hipLaunchKernelGGL(set_scalar_kernel, dim3(1), dim3(64), 0, s, p, v);
+  return hipGetLastError();
+}
+
+}  // namespace fockx

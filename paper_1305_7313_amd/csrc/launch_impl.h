@@ -1,0 +1,98 @@
+// Instantiates every plane / pencil kernel for one real type FX_T.
+#include "fock_launch.h"
+
+namespace fockx {
+
+namespace {
+template <int MODE, int N2, int N3>
+hipError_t plane_go(const PlaneArgs& a, int nblocks, hipStream_t s) {
+  using T = FX_T;
+  hipLaunchKernelGGL((plane_kernel<T, N2, N3, MODE>), dim3(nblocks), dim3(PlaneCfg<T, N2, N3>::W), 0, s, a);
+  return hipGetLastError();
+}
+template <int N2, int N3>
+hipError_t plane_mode(int mode, const PlaneArgs& a, int nblocks, hipStream_t s) {
+  switch (mode) {
+    case PLANE_PAIR_FWD: return plane_go<PLANE_PAIR_FWD, N2, N3>(a, nblocks, s);
+    case PLANE_INV_MAC: return plane_go<PLANE_INV_MAC, N2, N3>(a, nblocks, s);
+    case PLANE_FWD: return plane_go<PLANE_FWD, N2, N3>(a, nblocks, s);
+    case PLANE_INV: return plane_go<PLANE_INV, N2, N3>(a, nblocks, s);
+  }
+  return hipErrorInvalidValue;
+}
+template <int MODE, int N1>
+hipError_t pencil_go(const PencilArgs& a, int nblocks, hipStream_t s) {
+  using T = FX_T;
+  hipLaunchKernelGGL((pencil_kernel<T, N1, MODE>), dim3(nblocks), dim3(PencilCfg<T, N1>::W), 0, s, a);
+  return hipGetLastError();
+}
+template <int N1>
+hipError_t pencil_mode(int mode, const PencilArgs& a, int nblocks, hipStream_t s) {
+  switch (mode) {
+    case PENCIL_FKI: return pencil_go<PENCIL_FKI, N1>(a, nblocks, s);
+    case PENCIL_FE: return pencil_go<PENCIL_FE, N1>(a, nblocks, s);
+    case PENCIL_FWD: return pencil_go<PENCIL_FWD, N1>(a, nblocks, s);
+    case PENCIL_INV: return pencil_go<PENCIL_INV, N1>(a, nblocks, s);
+  }
+  return hipErrorInvalidValue;
+}
+}  // namespace
+
+template <>
+hipError_t launch_plane<FX_T>(int mode, int n2, int n3, const PlaneArgs& a, int nblocks, hipStream_t s) {
+#define FX_PLANE(A, B) \
+  if (n2 == A && n3 == B) return plane_mode<A, B>(mode, a, nblocks, s);
+  FX_PLANE(24, 24)
+  FX_PLANE(48, 48)
+  FX_PLANE(48, 64)
+  FX_PLANE(64, 64)
+  FX_PLANE(72, 72)
+  FX_PLANE(96, 96)
+  FX_PLANE(96, 128)
+#undef FX_PLANE
+  return hipErrorInvalidValue;
+}
+
+template <>
+hipError_t launch_pencil<FX_T>(int mode, int n1, const PencilArgs& a, int nblocks, hipStream_t s) {
+  switch (n1) {
+    case 24: return pencil_mode<24>(mode, a, nblocks, s);
+    case 48: return pencil_mode<48>(mode, a, nblocks, s);
+    case 64: return pencil_mode<64>(mode, a, nblocks, s);
+    case 72: return pencil_mode<72>(mode, a, nblocks, s);
+    case 96: return pencil_mode<96>(mode, a, nblocks, s);
+    case 128: return pencil_mode<128>(mode, a, nblocks, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <>
+hipError_t launch_zero<FX_T>(void* p, long long n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  long long blocks = (n + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(zero_kernel<FX_T>, dim3((unsigned)blocks), dim3(256), 0, s, reinterpret_cast<cx<FX_T>*>(p), n);
+  return hipGetLastError();
+}
+
+template <>
+hipError_t launch_scatter<FX_T>(const void* c, int ldc, const int* slot, int npw, int nb, void* box, long long N,
+                                hipStream_t s) {
+  if (nb <= 0 || npw <= 0) return hipSuccess;
+  const int bx = (npw + 255) / 256;
+  hipLaunchKernelGGL(scatter_kernel<FX_T>, dim3(bx, nb), dim3(256), 0, s, reinterpret_cast<const cx<FX_T>*>(c), ldc,
+                     slot, npw, reinterpret_cast<cx<FX_T>*>(box), N);
+  return hipGetLastError();
+}
+
+template <>
+hipError_t launch_gather<FX_T>(const void* box, long long N, const int* slot, int npw, int nj, void* out, int ldo,
+                               double s0, const double* w, int j0, const double* g, hipStream_t s) {
+  if (nj <= 0 || npw <= 0) return hipSuccess;
+  const int bx = (npw + 255) / 256;
+  hipLaunchKernelGGL(gather_kernel<FX_T>, dim3(bx, nj), dim3(256), 0, s, reinterpret_cast<const cx<FX_T>*>(box), N,
+                     slot, npw, reinterpret_cast<cx<FX_T>*>(out), ldo, s0, w, j0, g);
+  return hipGetLastError();
+}
+
+}  // namespace fockx

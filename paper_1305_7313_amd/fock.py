@@ -1,0 +1,232 @@
+"""ctypes binding of include/fock.h: argument marshalling only.
+
+Every step of the exchange path runs in libfockx.so.  PyTorch supplies device
+memory and the current HIP stream.  Loading fails loudly when the library
+has not been built (``python -c "import __graft_entry__ as g; g.build()"``).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfockx.so")
+
+FOCK_OK = 0
+FOCK_E_ARG = -1
+FOCK_E_ALIAS = -2
+FOCK_E_SINGULAR_Q = -3
+FOCK_E_WORKSPACE = -4
+FOCK_E_UNSUPPORTED_GRID = -5
+FOCK_E_HIP = -6
+FOCK_C128 = 0
+FOCK_C64 = 1
+FOCK_G0_ZERO = 0
+FOCK_G0_GB = 1
+
+
+class fock_cell(ctypes.Structure):
+    _fields_ = [
+        ("a", (ctypes.c_double * 3) * 3),
+        ("n", ctypes.c_int32 * 3),
+        ("npw", ctypes.c_int32),
+        ("miller", ctypes.POINTER(ctypes.c_int32)),
+        ("ecut_fock", ctypes.c_double),
+        ("g0", ctypes.c_int32),
+        ("gb_alpha", ctypes.c_double),
+        ("nq", ctypes.c_int32 * 3),
+    ]
+
+
+class fock_orbs(ctypes.Structure):
+    _fields_ = [
+        ("c", ctypes.c_void_p),
+        ("w", ctypes.c_void_p),
+        ("nb", ctypes.c_int32),
+        ("ld", ctypes.c_int32),
+    ]
+
+
+class FockError(RuntimeError):
+    def __init__(self, status: int, detail: str):
+        super().__init__(f"{status}: {detail}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it first (paper_1305_7313_amd/build.py)")
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.POINTER
+        L.fock_workspace_size.restype = ctypes.c_size_t
+        L.fock_workspace_size.argtypes = [P(fock_cell), ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
+        common = [P(fock_cell), P(ctypes.c_double), ctypes.c_int32, P(fock_orbs), P(fock_orbs)]
+        L.fock_apply.restype = ctypes.c_int
+        L.fock_apply.argtypes = common + [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
+        L.fock_energy.restype = ctypes.c_int
+        L.fock_energy.argtypes = common + [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
+        L.fock_energy_backward.restype = ctypes.c_int
+        L.fock_energy_backward.argtypes = common + [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                                    ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
+        L.fock_fft3d.restype = ctypes.c_int
+        L.fock_fft3d.argtypes = [P(ctypes.c_int32), ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                                 ctypes.c_int32, ctypes.c_void_p]
+        L.fock_status_string.restype = ctypes.c_char_p
+        L.fock_status_string.argtypes = [ctypes.c_int]
+        L.fock_last_error.restype = ctypes.c_char_p
+        L.fock_last_error.argtypes = []
+        L.fock_release_plans.restype = None
+        L.fock_release_plans.argtypes = []
+        _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != FOCK_OK:
+        detail = lib().fock_last_error().decode()
+        raise FockError(status, f"{lib().fock_status_string(status).decode()}: {detail}")
+
+
+class Cell:
+    """Host description of the cell, grid and sphere (keeps the Miller array alive)."""
+
+    def __init__(self, a, n, miller, ecut_fock: float = 0.0, g0: int = FOCK_G0_ZERO,
+                 gb_alpha: float = 0.0, nq=(1, 1, 1)):
+        self.a = np.ascontiguousarray(a, dtype=np.float64).reshape(3, 3)
+        self.n = tuple(int(x) for x in n)
+        self.miller = np.ascontiguousarray(miller, dtype=np.int32).reshape(-1, 3)
+        self.ecut_fock = float(ecut_fock)
+        self.g0 = int(g0)
+        self.gb_alpha = float(gb_alpha)
+        self.nq = tuple(int(x) for x in nq)
+        c = fock_cell()
+        for i in range(3):
+            for j in range(3):
+                c.a[i][j] = float(self.a[i, j])
+            c.n[i] = self.n[i]
+            c.nq[i] = self.nq[i]
+        c.npw = int(self.miller.shape[0])
+        c.miller = self.miller.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        c.ecut_fock = self.ecut_fock
+        c.g0 = self.g0
+        c.gb_alpha = self.gb_alpha
+        self.c = c
+
+    @property
+    def npw(self) -> int:
+        return int(self.miller.shape[0])
+
+
+def dtype_code(t) -> int:
+    import torch
+    if t.dtype == torch.complex128:
+        return FOCK_C128
+    if t.dtype == torch.complex64:
+        return FOCK_C64
+    raise TypeError(f"orbital coefficients must be complex128 or complex64, not {t.dtype}")
+
+
+def orbs(c, w) -> fock_orbs:
+    """fock_orbs over a device tensor c [nb, ld] (row-major) and weights w [nb] (float64)."""
+    import torch
+    if c.dim() != 2 or c.stride(1) != 1:
+        raise ValueError("coefficients must be [nb, ld] with unit stride along G")
+    if w.dtype != torch.float64 or not w.is_contiguous():
+        raise ValueError("weights must be a contiguous float64 tensor")
+    if w.numel() != c.shape[0]:
+        raise ValueError("one weight per orbital")
+    o = fock_orbs()
+    o.c = c.data_ptr() if c.numel() else None
+    o.w = w.data_ptr() if w.numel() else None
+    o.nb = int(c.shape[0])
+    o.ld = int(c.stride(0)) if c.shape[0] > 1 else int(c.shape[1])
+    return o
+
+
+def _stream(device=None):
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _qarr(q):
+    return (ctypes.c_double * 3)(*[float(x) for x in q])
+
+
+def fock_workspace_size(cell: Cell, dtype: int, n_occ: int, n_tgt: int) -> int:
+    return int(lib().fock_workspace_size(ctypes.byref(cell.c), int(dtype), int(n_occ), int(n_tgt)))
+
+
+def workspace(cell: Cell, dtype: int, n_occ: int, n_tgt: int, device):
+    import torch
+    nbytes = fock_workspace_size(cell, dtype, n_occ, n_tgt)
+    if nbytes == 0:
+        raise FockError(FOCK_E_UNSUPPORTED_GRID, "fock_workspace_size returned 0 for this cell")
+    return torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+
+def fock_apply(cell: Cell, q, c_occ, f_occ, c_tgt, out=None, ws=None):
+    """(V_x psi_j) on the sphere for every target: a [n_tgt, npw] tensor (C call: fock_apply)."""
+    import torch
+    dt = dtype_code(c_occ)
+    if out is None:
+        out = torch.empty((c_tgt.shape[0], cell.npw), dtype=c_tgt.dtype, device=c_tgt.device)
+    ones = torch.ones(c_tgt.shape[0], dtype=torch.float64, device=c_tgt.device)
+    o, t = orbs(c_occ, f_occ), orbs(c_tgt, ones)
+    if out.shape[0] > 1 and out.stride(0) != t.ld:
+        raise ValueError("out must have the targets' leading dimension")
+    if ws is None:
+        ws = workspace(cell, dt, o.nb, t.nb, c_occ.device)
+    _check(lib().fock_apply(ctypes.byref(cell.c), _qarr(q), dt, ctypes.byref(o), ctypes.byref(t),
+                            out.data_ptr() if out.numel() else None, ws.data_ptr(), ws.numel(),
+                            _stream(c_occ.device)))
+    return out
+
+
+def fock_energy(cell: Cell, q, c_occ, f_occ, c_tgt, g_tgt, out=None, ws=None):
+    """Exchange energy as a device float64 scalar tensor (C call: fock_energy)."""
+    import torch
+    dt = dtype_code(c_occ)
+    if out is None:
+        out = torch.empty((), dtype=torch.float64, device=c_occ.device)
+    o, t = orbs(c_occ, f_occ), orbs(c_tgt, g_tgt)
+    if ws is None:
+        ws = workspace(cell, dt, o.nb, t.nb, c_occ.device)
+    _check(lib().fock_energy(ctypes.byref(cell.c), _qarr(q), dt, ctypes.byref(o), ctypes.byref(t),
+                             out.data_ptr(), ws.data_ptr(), ws.numel(), _stream(c_occ.device)))
+    return out
+
+
+def fock_energy_backward(cell: Cell, q, c_occ, f_occ, c_tgt, g_tgt, grad_ex, grad_occ=None, grad_tgt=None,
+                         ws=None):
+    """Wirtinger gradients grad_ex * dE/dconj(c) into grad_occ / grad_tgt (C call: fock_energy_backward)."""
+    dt = dtype_code(c_occ)
+    o, t = orbs(c_occ, f_occ), orbs(c_tgt, g_tgt)
+    if ws is None:
+        ws = workspace(cell, dt, o.nb, t.nb, c_occ.device)
+    _check(lib().fock_energy_backward(
+        ctypes.byref(cell.c), _qarr(q), dt, ctypes.byref(o), ctypes.byref(t), grad_ex.data_ptr(),
+        grad_occ.data_ptr() if grad_occ is not None and grad_occ.numel() else None,
+        grad_tgt.data_ptr() if grad_tgt is not None and grad_tgt.numel() else None,
+        ws.data_ptr(), ws.numel(), _stream(c_occ.device)))
+    return grad_occ, grad_tgt
+
+
+def fock_fft3d(x, sign: int):
+    """In-place unnormalised 3-D transform of x [nb, n1, n2, n3] (C call: fock_fft3d)."""
+    n = (ctypes.c_int32 * 3)(*x.shape[-3:])
+    nb = int(np.prod(x.shape[:-3])) if x.dim() > 3 else 1
+    if not x.is_contiguous():
+        raise ValueError("x must be contiguous")
+    _check(lib().fock_fft3d(n, dtype_code(x), int(sign), x.data_ptr(), nb, _stream(x.device)))
+    return x
+
+
+def fock_release_plans():
+    lib().fock_release_plans()

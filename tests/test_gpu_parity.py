@@ -1,0 +1,183 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU FP64 oracle.
+
+Bars: FP64 path within 1e-10 relative (Frobenius over the whole block and
+per band); FP32 path within 1e-5 relative; energies |dE|/|E|.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import exx
+from tests.helpers import dev, host, max_row_rel, rel_fro, report
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"c128": 1e-10, "c64": 1e-5}
+
+
+def _F():
+    from paper_1305_7313_amd import fock
+    return fock
+
+
+def _ctype(name):
+    import torch
+    return torch.complex128 if name == "c128" else torch.complex64
+
+
+# ---------------------------------------------------------------------------
+# the transforms alone
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("n", [(24, 24, 24), (24, 48, 64), (48, 48, 48), (64, 64, 64), (72, 72, 72),
+                               (96, 96, 96), (96, 96, 128), (128, 96, 128)])
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_fft3d(n, prec):
+    F = _F()
+    rng = np.random.default_rng(sum(n))
+    x = rng.standard_normal((2,) + n) + 1j * rng.standard_normal((2,) + n)
+    print(f"[case] fft3d n={n} {prec}", flush=True)
+    for sign, ref in ((-1, exx.fft3(x, "fft")), (+1, exx.bfft3(x, "fft"))):
+        d = dev(x, _ctype(prec))
+        F.fock_fft3d(d, sign)
+        err = rel_fro(host(d), ref)
+        report(f"fft3d {n} {prec} sign={sign}", rel=err)
+        assert err < (1e-13 if prec == "c128" else 2e-6)
+
+
+# ---------------------------------------------------------------------------
+# config 1: 24^3, 8 occupied + 8 targets
+# ---------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def cfg1():
+    s, occ, tgt = synth.config1()
+    ones = np.ones(8)
+    v = exx.fock_apply(s.a, s.n, s.miller, np.zeros(3), occ, ones, tgt)
+    e = exx.fock_energy(s.a, s.n, s.miller, np.zeros(3), occ, ones, occ, ones)
+    return s, occ, tgt, v, e
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_config1_apply_energy(cfg1, prec):
+    import torch
+    F = _F()
+    s, occ, tgt, v_ref, e_ref = cfg1
+    print(f"[case] config1 {prec}", flush=True)
+    cell = F.Cell(s.a, s.n, s.miller)
+    co, ct = dev(occ, _ctype(prec)), dev(tgt, _ctype(prec))
+    f = torch.ones(8, dtype=torch.float64, device="cuda")
+    v = host(F.fock_apply(cell, (0, 0, 0), co, f, ct))
+    e = float(host(F.fock_energy(cell, (0, 0, 0), co, f, co, f)))
+    err_v, err_b, err_e = rel_fro(v, v_ref), max_row_rel(v, v_ref), abs(e - e_ref) / abs(e_ref)
+    report(f"config1 {prec}", apply_rel=err_v, apply_maxband=err_b, E=e, E_ref=e_ref, E_rel=err_e)
+    assert err_v < TOL[prec] and err_b < TOL[prec] and err_e < TOL[prec]
+
+
+# ---------------------------------------------------------------------------
+# ragged tiles, q != 0, non-uniform occupations, GB constant, skewed cell
+# ---------------------------------------------------------------------------
+CASES = {
+    "ragged_q": dict(a=synth.cubic_cell(10.0), n=(24, 24, 24), nocc=19, ntgt=21,
+                     q=(0.1, -0.05, 0.07), g0=0),
+    "ragged_gb": dict(a=synth.cubic_cell(10.0), n=(24, 24, 24), nocc=17, ntgt=5, q=(0.0, 0.0, 0.0), g0=1),
+    "skew_q": dict(a=np.array([[10.0, 0.0, 0.0], [1.0, 18.0, 0.0], [0.5, 0.3, 24.0]]), n=(24, 48, 64),
+                   nocc=6, ntgt=7, q=(0.03, 0.02, -0.04), g0=0),
+}
+
+
+@pytest.fixture(scope="module", params=sorted(CASES))
+def case(request):
+    c = CASES[request.param]
+    s = synth.make_system(c["a"], c["n"])
+    occ = synth.random_orbitals(s.a, s.miller, c["nocc"], 3)
+    tgt = synth.random_orbitals(s.a, s.miller, c["ntgt"], 4)
+    rng = np.random.default_rng(9)
+    f = rng.uniform(0.2, 1.0, c["nocc"])
+    g = rng.uniform(0.2, 1.0, c["ntgt"])
+    k0 = exx.gb_constant(s.a, s.n, (2, 2, 2), 0.7) if c["g0"] else 0.0
+    q = np.array(c["q"])
+    v = exx.fock_apply(s.a, s.n, s.miller, q, occ, f, tgt, k0=k0)
+    e = exx.fock_energy(s.a, s.n, s.miller, q, occ, f, tgt, g, k0=k0)
+    go, gt = exx.fock_energy_grad(s.a, s.n, s.miller, q, occ, f, tgt, g, k0=k0)
+    return request.param, c, s, occ, tgt, f, g, q, v, e, go, gt
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_cases_apply_energy_grad(case, prec):
+    import torch
+    F = _F()
+    name, c, s, occ, tgt, f, g, q, v_ref, e_ref, go_ref, gt_ref = case
+    print(f"[case] {name} {prec}", flush=True)
+    cell = F.Cell(s.a, s.n, s.miller, g0=c["g0"], gb_alpha=0.7, nq=(2, 2, 2))
+    co, ct = dev(occ, _ctype(prec)), dev(tgt, _ctype(prec))
+    fd, gd = dev(f), dev(g)
+    v = host(F.fock_apply(cell, q, co, fd, ct))
+    e = float(host(F.fock_energy(cell, q, co, fd, ct, gd)))
+    one = torch.ones((), dtype=torch.float64, device="cuda")
+    go, gt = torch.empty_like(co), torch.empty_like(ct)
+    F.fock_energy_backward(cell, q, co, fd, ct, gd, one, go, gt)
+    errs = dict(apply_rel=rel_fro(v, v_ref), apply_maxband=max_row_rel(v, v_ref),
+                E_rel=abs(e - e_ref) / abs(e_ref), gocc_rel=rel_fro(host(go), go_ref),
+                gtgt_rel=rel_fro(host(gt), gt_ref))
+    report(f"{name} {prec}", **errs)
+    for k, val in errs.items():
+        assert val < TOL[prec], (k, val)
+
+
+def test_band_group_split_sum(cfg1):
+    """Splitting the occupied sum into groups and adding the partial results
+    reproduces the full apply (the band-group reduction)."""
+    import torch
+    F = _F()
+    s, occ, tgt, v_ref, _ = cfg1
+    cell = F.Cell(s.a, s.n, s.miller)
+    co, ct = dev(occ), dev(tgt)
+    f = torch.ones(8, dtype=torch.float64, device="cuda")
+    full = F.fock_apply(cell, (0, 0, 0), co, f, ct)
+    parts = [F.fock_apply(cell, (0, 0, 0), co[a:b].contiguous(), f[a:b].contiguous(), ct)
+             for a, b in ((0, 3), (3, 5), (5, 8))]
+    tot = parts[0] + parts[1] + parts[2]
+    assert rel_fro(host(tot), host(full)) < 1e-13
+
+
+def test_energy_is_half_expectation():
+    import torch
+    F = _F()
+    s = synth.make_system(synth.cubic_cell(10.0), (24, 24, 24))
+    occ = synth.random_orbitals(s.a, s.miller, 20, 7)
+    f = np.linspace(1.0, 0.3, 20)
+    cell = F.Cell(s.a, s.n, s.miller)
+    co, fd = dev(occ), dev(f)
+    e = float(host(F.fock_energy(cell, (0, 0, 0), co, fd, co, fd)))
+    v = host(F.fock_apply(cell, (0, 0, 0), co, fd, co))
+    e2 = 0.5 * np.sum(f * np.einsum("ij,ij->i", np.conj(occ), v).real)
+    assert abs(e - e2) < 1e-12 * abs(e)
+
+
+def test_bitwise_reproducible(cfg1):
+    import torch
+    F = _F()
+    s, occ, tgt, _, _ = cfg1
+    cell = F.Cell(s.a, s.n, s.miller)
+    co, ct = dev(occ), dev(tgt)
+    f = torch.ones(8, dtype=torch.float64, device="cuda")
+    a1 = host(F.fock_apply(cell, (0, 0, 0), co, f, ct))
+    a2 = host(F.fock_apply(cell, (0, 0, 0), co, f, ct))
+    e1 = host(F.fock_energy(cell, (0, 0, 0), co, f, co, f))
+    e2 = host(F.fock_energy(cell, (0, 0, 0), co, f, co, f))
+    assert np.array_equal(a1, a2) and np.array_equal(e1, e2)
+
+
+def test_empty_blocks():
+    import torch
+    F = _F()
+    s, occ, tgt = synth.config1()
+    cell = F.Cell(s.a, s.n, s.miller)
+    co = dev(occ)
+    f = torch.ones(8, dtype=torch.float64, device="cuda")
+    empty = torch.empty((0, s.npw), dtype=torch.complex128, device="cuda")
+    e0 = torch.empty(0, dtype=torch.float64, device="cuda")
+    v = F.fock_apply(cell, (0, 0, 0), empty, e0, co)
+    assert float(host(v).__abs__().max()) == 0.0
+    assert float(host(F.fock_energy(cell, (0, 0, 0), co, f, empty, e0))) == 0.0
+    out = F.fock_apply(cell, (0, 0, 0), co, f, empty)
+    assert out.shape == (0, s.npw)
