@@ -118,6 +118,17 @@ fock_status fock_fft3d(const int32_t n[3], int32_t dtype, int32_t sign, void *x,
 const char *fock_status_string(fock_status status);
 const char *fock_last_error(void);
 
+/* Tracing aid: when enabled, every kernel launch of the calls above is
+ * bracketed by HIP events on its stream and attributed to a kernel class
+ * (orbital scatter, pair plane FFT, pencil kernel pass, ...).  Returns the
+ * number of classes. */
+int fock_trace_enable(int on);
+/* Accumulated milliseconds and launch counts per class since the last reset
+ * (arrays of fock_trace_enable()'s length; either may be NULL).  Waits for the
+ * recorded events.  reset != 0 clears the totals. */
+int fock_trace_read(double *ms_out, long long *count_out, int reset);
+const char *fock_trace_name(int k);
+
 /* Free every cached plan (twiddle tables, sphere index tables) of this process. */
 void fock_release_plans(void);
 

@@ -27,6 +27,56 @@ fock_status fail(fock_status s, const std::string& msg) {
 }
 
 // ---------------------------------------------------------------------------
+// Per-kernel-class timing with HIP events (off unless fock_trace_enable(1)).
+// ---------------------------------------------------------------------------
+enum KClass : int {
+  KC_A1_SCATTER = 0, KC_A1_PENCIL, KC_A1_PLANE, KC_P1, KC_P2, KC_P2E, KC_P3,
+  KC_A7_PLANE, KC_A7_PENCIL, KC_A7_GATHER, KC_REDUCE, KC_ZERO, KC_COUNT
+};
+const char* const kClassNames[KC_COUNT] = {
+    "a1_scatter", "a1_pencil_inv", "a1_plane_inv", "p1_pair_plane_fwd", "p2_pencil_kernel",
+    "p2_pencil_energy", "p3_plane_inv_mac", "a7_plane_fwd", "a7_pencil_fwd", "a7_gather",
+    "reduce", "zero_fill"};
+
+struct Tracer {
+  std::mutex m;
+  bool on = false;
+  struct Rec { int k; hipEvent_t a, b; };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;
+  double ms[KC_COUNT] = {};
+  long long n[KC_COUNT] = {};
+  hipEvent_t take() {
+    if (!pool.empty()) { hipEvent_t e = pool.back(); pool.pop_back(); return e; }
+    hipEvent_t e = nullptr;
+    (void)hipEventCreate(&e);
+    return e;
+  }
+};
+Tracer& tracer() { static Tracer* t = new Tracer(); return *t; }
+
+struct TraceScope {
+  int k; hipStream_t s; hipEvent_t a = nullptr, b = nullptr; bool on;
+  TraceScope(int kc, hipStream_t st) : k(kc), s(st) {
+    Tracer& T = tracer();
+    on = T.on;
+    if (on) {
+      std::lock_guard<std::mutex> lk(T.m);
+      a = T.take(); b = T.take();
+      (void)hipEventRecord(a, s);
+    }
+  }
+  ~TraceScope() {
+    if (!on) return;
+    Tracer& T = tracer();
+    (void)hipEventRecord(b, s);
+    std::lock_guard<std::mutex> lk(T.m);
+    T.recs.push_back({k, a, b});
+  }
+};
+#define FX_TRACE(kc) TraceScope trace_scope_##__LINE__(kc, s)
+
+// ---------------------------------------------------------------------------
 // Plans: per device, grid, lattice, dtype and sphere.
 // ---------------------------------------------------------------------------
 struct Plan {
@@ -283,8 +333,11 @@ struct Engine {
 
   fock_status to_real_space(const void* c, int ld, int nb, void* box) {
     if (nb <= 0) return FOCK_OK;
-    FX_HIP(launch_zero<T>(box, P.N * nb, s));
-    FX_HIP(launch_scatter<T>(c, ld, P.d_slot, P.npw, nb, box, P.N, s));
+    {
+      FX_TRACE(KC_A1_SCATTER);
+      FX_HIP(launch_zero<T>(box, P.N * nb, s));
+      FX_HIP(launch_scatter<T>(c, ld, P.d_slot, P.npw, nb, box, P.N, s));
+    }
     return transform(box, nb, +1);
   }
 
@@ -304,11 +357,11 @@ struct Engine {
     la.n1 = P.n[0];
     la.nb = nb;
     if (sign > 0) {
-      FX_HIP(launch_pencil<T>(PENCIL_INV, P.n[0], pa, nb * ngroups, s));
-      FX_HIP(launch_plane<T>(PLANE_INV, P.n[1], P.n[2], la, nb * P.n[0], s));
+      { FX_TRACE(KC_A1_PENCIL); FX_HIP(launch_pencil<T>(PENCIL_INV, P.n[0], pa, nb * ngroups, s)); }
+      { FX_TRACE(KC_A1_PLANE); FX_HIP(launch_plane<T>(PLANE_INV, P.n[1], P.n[2], la, nb * P.n[0], s)); }
     } else {
-      FX_HIP(launch_plane<T>(PLANE_FWD, P.n[1], P.n[2], la, nb * P.n[0], s));
-      FX_HIP(launch_pencil<T>(PENCIL_FWD, P.n[0], pa, nb * ngroups, s));
+      { FX_TRACE(KC_A7_PLANE); FX_HIP(launch_plane<T>(PLANE_FWD, P.n[1], P.n[2], la, nb * P.n[0], s)); }
+      { FX_TRACE(KC_A7_PENCIL); FX_HIP(launch_pencil<T>(PENCIL_FWD, P.n[0], pa, nb * ngroups, s)); }
     }
     return FOCK_OK;
   }
@@ -351,7 +404,10 @@ struct Engine {
     int tile = 0;
     for (int j0 = 0; j0 < nB; j0 += t.tj) {
       const int tj = (nB - j0) < t.tj ? (nB - j0) : t.tj;
-      if (!energy) FX_HIP(launch_zero<T>(acc, P.N * tj, s));
+      if (!energy) {
+        FX_TRACE(KC_ZERO);
+        FX_HIP(launch_zero<T>(acc, P.N * tj, s));
+      }
       for (int i0 = 0; i0 < nA; i0 += t.ti, ++tile) {
         const int ti = (nA - i0) < t.ti ? (nA - i0) : t.ti;
         PlaneArgs la{};
@@ -369,7 +425,10 @@ struct Engine {
         la.tj = tj;
         la.n1 = P.n[0];
         la.fscale = 1.0;
-        FX_HIP(launch_plane<T>(PLANE_PAIR_FWD, P.n[1], P.n[2], la, ti * tj * P.n[0], s));
+        {
+          FX_TRACE(KC_P1);
+          FX_HIP(launch_plane<T>(PLANE_PAIR_FWD, P.n[1], P.n[2], la, ti * tj * P.n[0], s));
+        }
         PencilArgs pa{};
         pa.x = w;
         pa.epart = energy ? epart : nullptr;
@@ -380,18 +439,19 @@ struct Engine {
         pa.n3 = P.n[2];
         pa.count = ti * tj;
         if (energy) {
-          FX_HIP(launch_pencil<T>(PENCIL_FE, P.n[0], pa, ti * tj * ngroups, s));
+          { FX_TRACE(KC_P2E); FX_HIP(launch_pencil<T>(PENCIL_FE, P.n[0], pa, ti * tj * ngroups, s)); }
           // epart is laid out [ii*tj + jj][group]
-          FX_HIP(launch_energy_tile(epart, ngroups, fA, gB, i0, j0, ti, tj, nullptr, tile_e + tile, s));
+          { FX_TRACE(KC_REDUCE); FX_HIP(launch_energy_tile(epart, ngroups, fA, gB, i0, j0, ti, tj, nullptr, tile_e + tile, s)); }
         } else {
-          FX_HIP(launch_pencil<T>(PENCIL_FKI, P.n[0], pa, ti * tj * ngroups, s));
-          FX_HIP(launch_plane<T>(PLANE_INV_MAC, P.n[1], P.n[2], la, tj * P.n[0], s));
+          { FX_TRACE(KC_P2); FX_HIP(launch_pencil<T>(PENCIL_FKI, P.n[0], pa, ti * tj * ngroups, s)); }
+          { FX_TRACE(KC_P3); FX_HIP(launch_plane<T>(PLANE_INV_MAC, P.n[1], P.n[2], la, tj * P.n[0], s)); }
         }
       }
       if (!energy) {
         fock_status st = transform(acc, tj, -1);
         if (st != FOCK_OK) return st;
         char* o = static_cast<char*>(out) + (size_t)j0 * ldo * sizeof(cx<T>);
+        FX_TRACE(KC_A7_GATHER);
         FX_HIP(launch_gather<T>(acc, P.N, P.d_slot, P.npw, tj, o, ldo, s0, wout, j0, gscale, s));
       }
     }
@@ -609,6 +669,39 @@ const char* fock_status_string(fock_status st) {
 }
 
 const char* fock_last_error(void) { return g_last_error.c_str(); }
+
+int fock_trace_enable(int on) {
+  Tracer& T = tracer();
+  std::lock_guard<std::mutex> lk(T.m);
+  T.on = on != 0;
+  return KC_COUNT;
+}
+
+int fock_trace_read(double* ms_out, long long* count_out, int reset) {
+  Tracer& T = tracer();
+  std::lock_guard<std::mutex> lk(T.m);
+  for (auto& r : T.recs) {
+    float ms = 0.0f;
+    if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+      T.ms[r.k] += ms;
+      T.n[r.k] += 1;
+    }
+    T.pool.push_back(r.a);
+    T.pool.push_back(r.b);
+  }
+  T.recs.clear();
+  for (int k = 0; k < KC_COUNT; ++k) {
+    if (ms_out) ms_out[k] = T.ms[k];
+    if (count_out) count_out[k] = T.n[k];
+    if (reset) {
+      T.ms[k] = 0.0;
+      T.n[k] = 0;
+    }
+  }
+  return KC_COUNT;
+}
+
+const char* fock_trace_name(int k) { return (k >= 0 && k < KC_COUNT) ? kClassNames[k] : ""; }
 
 void fock_release_plans(void) {
   std::lock_guard<std::mutex> lk(g_mutex);

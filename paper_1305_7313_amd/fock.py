@@ -82,6 +82,13 @@ def lib():
         L.fock_status_string.argtypes = [ctypes.c_int]
         L.fock_last_error.restype = ctypes.c_char_p
         L.fock_last_error.argtypes = []
+        L.fock_trace_enable.restype = ctypes.c_int
+        L.fock_trace_enable.argtypes = [ctypes.c_int]
+        L.fock_trace_read.restype = ctypes.c_int
+        L.fock_trace_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_longlong),
+                                      ctypes.c_int]
+        L.fock_trace_name.restype = ctypes.c_char_p
+        L.fock_trace_name.argtypes = [ctypes.c_int]
         L.fock_release_plans.restype = None
         L.fock_release_plans.argtypes = []
         _lib = L
@@ -230,3 +237,16 @@ def fock_fft3d(x, sign: int):
 
 def fock_release_plans():
     lib().fock_release_plans()
+
+
+def fock_trace_enable(on: bool) -> int:
+    return int(lib().fock_trace_enable(1 if on else 0))
+
+
+def fock_trace_read(reset: bool = True) -> dict:
+    """{kernel class: (milliseconds, launches)} accumulated since the last reset."""
+    n = int(lib().fock_trace_read(None, None, 0))
+    ms = (ctypes.c_double * n)()
+    cnt = (ctypes.c_longlong * n)()
+    lib().fock_trace_read(ms, cnt, 1 if reset else 0)
+    return {lib().fock_trace_name(k).decode(): (float(ms[k]), int(cnt[k])) for k in range(n)}
