@@ -30,12 +30,12 @@ fock_status fail(fock_status s, const std::string& msg) {
 // Per-kernel-class timing with HIP events (off unless fock_trace_enable(1)).
 // ---------------------------------------------------------------------------
 enum KClass : int {
-  KC_A1_SCATTER = 0, KC_A1_PENCIL, KC_A1_PLANE, KC_P1, KC_P2, KC_P2E, KC_P3,
+  KC_A1_SCATTER = 0, KC_A1_PENCIL, KC_A1_PLANE, KC_P1, KC_P2, KC_P2E, KC_P3, KC_P3B,
   KC_A7_PLANE, KC_A7_PENCIL, KC_A7_GATHER, KC_REDUCE, KC_ZERO, KC_COUNT
 };
 const char* const kClassNames[KC_COUNT] = {
     "a1_scatter", "a1_pencil_inv", "a1_plane_inv", "p1_pair_plane_fwd", "p2_pencil_kernel",
-    "p2_pencil_energy", "p3_plane_inv_mac", "a7_plane_fwd", "a7_pencil_fwd", "a7_gather",
+    "p2_pencil_energy", "p3_plane_inv_mac", "p3_mirror_mac", "a7_plane_fwd", "a7_pencil_fwd", "a7_gather",
     "reduce", "zero_fill"};
 
 struct Tracer {
@@ -150,9 +150,11 @@ hipError_t upload_twiddles(int n, int dtype, void** out) {
                    hipMemcpyHostToDevice);
 }
 
-bool grid_supported(const int n[3]) {
+int tbytes_of(int dtype) { return dtype == FOCK_C128 ? 8 : 4; }
+
+bool grid_supported(const int n[3], int dtype) {
   if (!size_ok(n[0]) || !plane_supported(n[1], n[2])) return false;
-  const int cb = pencil_columns(n[0]);
+  const int cb = pencil_columns(n[0], tbytes_of(dtype));
   return cb > 0 && (n[1] * n[2]) % cb == 0;
 }
 
@@ -192,7 +194,7 @@ fock_status get_plan(const fock_cell* cell, int dtype, std::shared_ptr<Plan>* ou
   if (dtype != FOCK_C128 && dtype != FOCK_C64) return fail(FOCK_E_ARG, "dtype must be FOCK_C128 or FOCK_C64");
   for (int k = 0; k < 3; ++k)
     if (cell->n[k] <= 0) return fail(FOCK_E_ARG, "grid sizes must be positive");
-  if (!grid_supported(cell->n))
+  if (!grid_supported(cell->n, dtype))
     return fail(FOCK_E_UNSUPPORTED_GRID, "no compiled transforms for grid " + grid_str(cell->n));
   if (cell->npw <= 0 || !cell->miller) return fail(FOCK_E_ARG, "empty G-sphere (npw <= 0 or miller NULL)");
   for (int i = 0; i < 3; ++i)
@@ -329,7 +331,9 @@ struct Engine {
   const Plan& P;
   hipStream_t s;
   int ngroups;
-  Engine(const Plan& p, hipStream_t st) : P(p), s(st) { ngroups = P.n[1] * P.n[2] / pencil_columns(P.n[0]); }
+  Engine(const Plan& p, hipStream_t st) : P(p), s(st) {
+    ngroups = P.n[1] * P.n[2] / pencil_columns(P.n[0], (int)sizeof(T));
+  }
 
   fock_status to_real_space(const void* c, int ld, int nb, void* box) {
     if (nb <= 0) return FOCK_OK;
@@ -390,71 +394,135 @@ struct Engine {
     return FOCK_OK;
   }
 
-  // The band-pair loop.  mode 0: apply -> out; mode 1: energy partials -> tile_e.
+  PlaneArgs plane_args(const void* phiA, const void* phiB, void* w, void* acc, const double* f, int i0, int j0,
+                       int ti, int tj) {
+    PlaneArgs la{};
+    la.a = phiA;
+    la.bsrc = phiB;
+    la.w = w;
+    la.acc = acc;
+    la.f = f;
+    la.tw2 = P.d_tw[1];
+    la.tw3 = P.d_tw[2];
+    la.N = P.N;
+    la.i0 = i0;
+    la.j0 = j0;
+    la.ti = ti;
+    la.tj = tj;
+    la.n1 = P.n[0];
+    la.fscale = 1.0;
+    return la;
+  }
+
+  // P1 and P2 of one pair tile (energy: P2 only accumulates partials).
+  fock_status tile_forward(const PlaneArgs& la, const KernelParams& kp, bool energy, double* epart) {
+    const int tt = la.ti * la.tj;
+    {
+      FX_TRACE(KC_P1);
+      FX_HIP(launch_plane<T>(PLANE_PAIR_FWD, P.n[1], P.n[2], la, tt * P.n[0], s));
+    }
+    PencilArgs pa{};
+    pa.x = la.w;
+    pa.epart = energy ? epart : nullptr;
+    pa.tw1 = P.d_tw[0];
+    pa.kp = kp;
+    pa.N = P.N;
+    pa.n2 = P.n[1];
+    pa.n3 = P.n[2];
+    pa.count = tt;
+    if (energy) {
+      FX_TRACE(KC_P2E);
+      FX_HIP(launch_pencil<T>(PENCIL_FE, P.n[0], pa, tt * ngroups, s));
+    } else {
+      FX_TRACE(KC_P2);
+      FX_HIP(launch_pencil<T>(PENCIL_FKI, P.n[0], pa, tt * ngroups, s));
+    }
+    return FOCK_OK;
+  }
+
+  // acc[0..nj) (real space) -> forward FFT -> sphere rows j0.. of out, scaled.
+  fock_status finish(void* acc, int nj, int j0, void* out, int ldo, double s0, const double* wout,
+                     const double* gscale) {
+    fock_status st = transform(acc, nj, -1);
+    if (st != FOCK_OK) return st;
+    char* o = static_cast<char*>(out) + (size_t)j0 * ldo * sizeof(cx<T>);
+    FX_TRACE(KC_A7_GATHER);
+    FX_HIP(launch_gather<T>(acc, P.N, P.d_slot, P.npw, nj, o, ldo, s0, wout, j0, gscale, s));
+    return FOCK_OK;
+  }
+
+  // The band-pair loop.  energy == false: apply -> out; true: energy partials -> tile_e.
+  // sym: one orbital block at q = 0; only tiles I <= J are transformed, and
+  // v_ji = conj(v_ij) supplies the mirrored pairs.
   fock_status pairs(const fock_cell* cell, const double q[3], bool q_zero, const void* phiA, const double* fA,
                     int nA, const void* phiB, const double* gB, int nB, char* ws, const Layout& L, bool energy,
-                    void* out, int ldo, double s0, const double* wout, const double* gscale) {
+                    bool sym, void* out, int ldo, double s0, const double* wout, const double* gscale) {
     const Tiles t = tiles_for(nA, nB);
-    void* acc = ws + L.acc;
     void* w = ws + L.w;
     double* epart = reinterpret_cast<double*>(ws + L.epart);
     double* tile_e = reinterpret_cast<double*>(ws + L.tile_e);
     double* d_k0 = reinterpret_cast<double*>(ws + L.k0);
     KernelParams kp = kparams(q, q_zero, cell, d_k0);
+    fock_status st;
     int tile = 0;
-    for (int j0 = 0; j0 < nB; j0 += t.tj) {
-      const int tj = (nB - j0) < t.tj ? (nB - j0) : t.tj;
-      if (!energy) {
-        FX_TRACE(KC_ZERO);
-        FX_HIP(launch_zero<T>(acc, P.N * tj, s));
-      }
-      for (int i0 = 0; i0 < nA; i0 += t.ti, ++tile) {
-        const int ti = (nA - i0) < t.ti ? (nA - i0) : t.ti;
-        PlaneArgs la{};
-        la.a = phiA;
-        la.bsrc = phiB;
-        la.w = w;
-        la.acc = acc;
-        la.f = fA;
-        la.tw2 = P.d_tw[1];
-        la.tw3 = P.d_tw[2];
-        la.N = P.N;
-        la.i0 = i0;
-        la.j0 = j0;
-        la.ti = ti;
-        la.tj = tj;
-        la.n1 = P.n[0];
-        la.fscale = 1.0;
-        {
-          FX_TRACE(KC_P1);
-          FX_HIP(launch_plane<T>(PLANE_PAIR_FWD, P.n[1], P.n[2], la, ti * tj * P.n[0], s));
+    if (!sym) {
+      void* acc = ws + L.acc;
+      for (int j0 = 0; j0 < nB; j0 += t.tj) {
+        const int tj = (nB - j0) < t.tj ? (nB - j0) : t.tj;
+        if (!energy) {
+          FX_TRACE(KC_ZERO);
+          FX_HIP(launch_zero<T>(acc, P.N * tj, s));
         }
-        PencilArgs pa{};
-        pa.x = w;
-        pa.epart = energy ? epart : nullptr;
-        pa.tw1 = P.d_tw[0];
-        pa.kp = kp;
-        pa.N = P.N;
-        pa.n2 = P.n[1];
-        pa.n3 = P.n[2];
-        pa.count = ti * tj;
+        for (int i0 = 0; i0 < nA; i0 += t.ti, ++tile) {
+          const int ti = (nA - i0) < t.ti ? (nA - i0) : t.ti;
+          PlaneArgs la = plane_args(phiA, phiB, w, acc, fA, i0, j0, ti, tj);
+          if ((st = tile_forward(la, kp, energy, epart)) != FOCK_OK) return st;
+          if (energy) {
+            FX_TRACE(KC_REDUCE);
+            FX_HIP(launch_energy_tile(epart, ngroups, fA, gB, i0, j0, ti, tj, 0, tile_e + tile, s));
+          } else {
+            FX_TRACE(KC_P3);
+            FX_HIP(launch_plane<T>(PLANE_INV_MAC, P.n[1], P.n[2], la, tj * P.n[0], s));
+          }
+        }
+        if (!energy && (st = finish(acc, tj, j0, out, ldo, s0, wout, gscale)) != FOCK_OK) return st;
+      }
+      return FOCK_OK;
+    }
+    // symmetric schedule: accumulators for every orbital live in the (unused) phiB region
+    const int T0 = t.ti;
+    void* acc_all = ws + L.phiB;
+    if (!energy) {
+      FX_TRACE(KC_ZERO);
+      FX_HIP(launch_zero<T>(acc_all, P.N * nB, s));
+    }
+    for (int j0 = 0; j0 < nB; j0 += T0) {
+      const int tj = (nB - j0) < T0 ? (nB - j0) : T0;
+      for (int i0 = 0; i0 <= j0; i0 += T0, ++tile) {
+        const int ti = (nA - i0) < T0 ? (nA - i0) : T0;
+        char* accJ = static_cast<char*>(acc_all) + (size_t)j0 * P.N * sizeof(cx<T>);
+        PlaneArgs la = plane_args(phiA, phiA, w, accJ, fA, i0, j0, ti, tj);
+        if ((st = tile_forward(la, kp, energy, epart)) != FOCK_OK) return st;
         if (energy) {
-          { FX_TRACE(KC_P2E); FX_HIP(launch_pencil<T>(PENCIL_FE, P.n[0], pa, ti * tj * ngroups, s)); }
-          // epart is laid out [ii*tj + jj][group]
-          { FX_TRACE(KC_REDUCE); FX_HIP(launch_energy_tile(epart, ngroups, fA, gB, i0, j0, ti, tj, nullptr, tile_e + tile, s)); }
-        } else {
-          { FX_TRACE(KC_P2); FX_HIP(launch_pencil<T>(PENCIL_FKI, P.n[0], pa, ti * tj * ngroups, s)); }
-          { FX_TRACE(KC_P3); FX_HIP(launch_plane<T>(PLANE_INV_MAC, P.n[1], P.n[2], la, tj * P.n[0], s)); }
+          FX_TRACE(KC_REDUCE);
+          FX_HIP(launch_energy_tile(epart, ngroups, fA, gB, i0, j0, ti, tj, 1, tile_e + tile, s));
+          continue;
         }
-      }
-      if (!energy) {
-        fock_status st = transform(acc, tj, -1);
-        if (st != FOCK_OK) return st;
-        char* o = static_cast<char*>(out) + (size_t)j0 * ldo * sizeof(cx<T>);
-        FX_TRACE(KC_A7_GATHER);
-        FX_HIP(launch_gather<T>(acc, P.N, P.d_slot, P.npw, tj, o, ldo, s0, wout, j0, gscale, s));
+        la.store_v = i0 != j0;
+        {
+          FX_TRACE(KC_P3);
+          FX_HIP(launch_plane<T>(PLANE_INV_MAC, P.n[1], P.n[2], la, tj * P.n[0], s));
+        }
+        if (i0 != j0) {
+          // acc_i += sum_j f_j phi_j conj(v_ij)
+          PlaneArgs lb = la;
+          lb.acc = static_cast<char*>(acc_all) + (size_t)i0 * P.N * sizeof(cx<T>);
+          FX_TRACE(KC_P3B);
+          FX_HIP(launch_mac_conj<T>(lb, P.n[1] * P.n[2], ti * P.n[0], s));
+        }
       }
     }
+    if (!energy && (st = finish(acc_all, nB, 0, out, ldo, s0, wout, gscale)) != FOCK_OK) return st;
     return FOCK_OK;
   }
 };
@@ -486,8 +554,8 @@ fock_status apply_impl(const fock_cell* cell, const Plan& P, const double q[3], 
     }
     return FOCK_OK;
   }
-  return E.pairs(cell, q, q_zero, phiA, occ->w, occ->nb, phiB, tgt->w, tgt->nb, ws, L, false, out, tgt->ld, s0, wout,
-                 gscale);
+  return E.pairs(cell, q, q_zero, phiA, occ->w, occ->nb, phiB, tgt->w, tgt->nb, ws, L, false, same && q_zero, out,
+                 tgt->ld, s0, wout, gscale);
 }
 
 template <typename T>
@@ -507,11 +575,13 @@ fock_status energy_impl(const fock_cell* cell, const Plan& P, const double q[3],
   if ((st = E.to_real_space(occ->c, occ->ld, occ->nb, phiA)) != FOCK_OK) return st;
   if (same) phiB = phiA;
   else if ((st = E.to_real_space(tgt->c, tgt->ld, tgt->nb, phiB)) != FOCK_OK) return st;
-  st = E.pairs(cell, q, q_zero, phiA, occ->w, occ->nb, phiB, tgt->w, tgt->nb, ws, L, true, nullptr, 0, 0.0, nullptr,
-               nullptr);
+  const bool sym = same && q_zero;
+  st = E.pairs(cell, q, q_zero, phiA, occ->w, occ->nb, phiB, tgt->w, tgt->nb, ws, L, true, sym, nullptr, 0, 0.0,
+               nullptr, nullptr);
   if (st != FOCK_OK) return st;
   const Tiles t = tiles_for(occ->nb, tgt->nb);
-  const int ntiles = ((occ->nb + t.ti - 1) / t.ti) * ((tgt->nb + t.tj - 1) / t.tj);
+  const int nti = (occ->nb + t.ti - 1) / t.ti, ntj = (tgt->nb + t.tj - 1) / t.tj;
+  const int ntiles = sym ? nti * (nti + 1) / 2 : nti * ntj;
   const double scale = -0.5 / (P.omega * (double)P.N * (double)P.N);
   FX_HIP(launch_energy_final(reinterpret_cast<double*>(ws + L.tile_e), ntiles, scale, ex, s));
   return FOCK_OK;
@@ -557,13 +627,13 @@ fock_status prepare(const fock_cell* cell, const double q[3], int dtype, const f
                     void* ws, size_t ws_bytes, Prepared* out) {
   fock_status st = check_cell_host(cell, dtype);
   if (st != FOCK_OK) return st;
-  if (!grid_supported(cell->n))
+  if (!grid_supported(cell->n, dtype))
     return fail(FOCK_E_UNSUPPORTED_GRID, "no compiled transforms for grid " + grid_str(cell->n));
   if ((st = check_orbs(occ, cell->npw, "occ")) != FOCK_OK) return st;
   if ((st = check_orbs(tgt, cell->npw, "tgt")) != FOCK_OK) return st;
   if ((st = check_q(cell, q, &out->q_zero)) != FOCK_OK) return st;
   const long long N = (long long)cell->n[0] * cell->n[1] * cell->n[2];
-  const int ngroups = cell->n[1] * cell->n[2] / pencil_columns(cell->n[0]);
+  const int ngroups = cell->n[1] * cell->n[2] / pencil_columns(cell->n[0], tbytes_of(dtype));
   out->L = layout(N, dtype == FOCK_C128 ? 16 : 8, ngroups, occ->nb, tgt->nb);
   if (!ws || ws_bytes < out->L.total) {
     char buf[160];
@@ -579,9 +649,9 @@ extern "C" {
 
 size_t fock_workspace_size(const fock_cell* cell, int32_t dtype, int32_t n_occ, int32_t n_tgt) {
   if (!cell || n_occ < 0 || n_tgt < 0 || (dtype != FOCK_C128 && dtype != FOCK_C64)) return 0;
-  if (!grid_supported(cell->n)) return 0;
+  if (!grid_supported(cell->n, dtype)) return 0;
   const long long N = (long long)cell->n[0] * cell->n[1] * cell->n[2];
-  const int ngroups = cell->n[1] * cell->n[2] / pencil_columns(cell->n[0]);
+  const int ngroups = cell->n[1] * cell->n[2] / pencil_columns(cell->n[0], tbytes_of(dtype));
   return layout(N, dtype == FOCK_C128 ? 16 : 8, ngroups, n_occ, n_tgt).total;
 }
 
@@ -646,7 +716,7 @@ fock_status fock_fft3d(const int32_t n[3], int32_t dtype, int32_t sign, void* x,
   if (nb < 0) return fail(FOCK_E_ARG, "nb < 0");
   if (nb > 0 && !x) return fail(FOCK_E_ARG, "x is NULL");
   int nn[3] = {n[0], n[1], n[2]};
-  if (!grid_supported(nn)) return fail(FOCK_E_UNSUPPORTED_GRID, "no compiled transforms for grid " + grid_str(nn));
+  if (!grid_supported(nn, dtype)) return fail(FOCK_E_UNSUPPORTED_GRID, "no compiled transforms for grid " + grid_str(nn));
   std::shared_ptr<Plan> p;
   fock_status st = make_fft_plan(nn, dtype, &p);
   if (st != FOCK_OK) return st;

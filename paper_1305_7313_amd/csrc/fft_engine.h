@@ -9,7 +9,7 @@
 // y[(i - k) R + k + r P].  After the last pass the output is in natural order.
 //
 // Values live in registers across a pass; between passes they are exchanged
-// through LDS (padded by one slot every 32 to spread banks).  The first pass
+// through LDS (rows padded by one element to spread banks).  The first pass
 // of a transform can read straight from HBM and the last can write straight
 // to HBM, so a whole 2-D transform costs one HBM read and one HBM write.
 //
@@ -203,8 +203,15 @@ template <int R, int DIR, typename T> __device__ __forceinline__ void dft(cx<T>*
 // One autosort pass over a tile held by W threads.
 //   L      transform length, R radix, P span (product of earlier radices)
 //   BATCH  number of transforms in the tile
-//   ROW    true: transform along the contiguous axis, tile pos = b*L + x
-//          false: along the strided axis,             tile pos = x*BATCH + b
+//   ROW    true: transform along the contiguous axis: element (b, x) is at
+//          tile row b, column x; lanes walk the butterfly index i first
+//          false: along the strided axis: element (b, x) is at row x,
+//          column b; lanes walk the column b first
+//   SL     row stride of the tile in LDS (padded; in elements)
+// Thread t owns butterflies beta = t + s W, s < NS.  W is a multiple of the
+// lane-fastest extent (NI for ROW, BATCH for COL), so (b, i) are affine in s
+// and every element position is base(t) + constant: the per-element offsets
+// fold into instruction immediates.
 // ---------------------------------------------------------------------------
 template <int L_, int R_, int P_, int BATCH_, bool ROW_, int W_> struct Pass {
   static constexpr int L = L_, R = R_, P = P_, BATCH = BATCH_, W = W_;
@@ -214,25 +221,39 @@ template <int L_, int R_, int P_, int BATCH_, bool ROW_, int W_> struct Pass {
   static constexpr int NS = (NBF + W - 1) / W;
   static constexpr bool EXACT = (NBF % W) == 0;
   static constexpr int NV = NS * R;          // register values per thread
+  static constexpr int FAST = ROW ? NI : BATCH;
   static_assert(L % R == 0 && L % (P * R) == 0, "bad pass");
+  static_assert(P == 1 || P == NI, "two-pass factorisations only");
+  static_assert(W % FAST == 0, "block size must be a multiple of the lane-fastest extent");
+  static constexpr int STEP = W / FAST;      // per-slot increment of the slow index
 
-  __device__ static __forceinline__ bool get(int t, int s, int& b, int& i) {
-    const int beta = t + s * W;
+  struct Lane {
+    int b0, i0;   // slot-0 batch index and butterfly index
+    int tlim;     // last slot active iff t < tlim
+  };
+  __device__ static __forceinline__ Lane lane(int t) {
+    Lane l;
     if constexpr (ROW) {
-      i = beta % NI;
-      b = beta / NI;
+      l.i0 = t % NI;
+      l.b0 = t / NI;
     } else {
-      b = beta % BATCH;
-      i = beta / BATCH;
+      l.b0 = t % BATCH;
+      l.i0 = t / BATCH;
     }
-    return EXACT || beta < NBF;
+    l.tlim = NBF - (NS - 1) * W;
+    return l;
+  }
+  __device__ static __forceinline__ int b_of(const Lane& l, int s) { return ROW ? l.b0 + s * STEP : l.b0; }
+  __device__ static __forceinline__ int i_of(const Lane& l, int s) { return ROW ? l.i0 : l.i0 + s * STEP; }
+  __device__ static __forceinline__ bool active(const Lane& l, int t, int s) {
+    return EXACT || s < NS - 1 || t < l.tlim;
   }
   __device__ static __forceinline__ int in_x(int i, int r) { return i + r * NI; }
-  __device__ static __forceinline__ int out_x(int i, int r) {
-    const int k = i % P;
-    return (i - k) * R + k + r * P;
-  }
-  __device__ static __forceinline__ int pos(int b, int x) { return ROW ? b * L + x : x * BATCH + b; }
+  // P == 1: k = 0;  P == NI (last pass of two): i < P so k = i
+  __device__ static __forceinline__ int out_x(int i, int r) { return P == 1 ? i * R + r : i + r * P; }
+  // (b, x) -> (row, col) of the tile
+  __device__ static __forceinline__ int row_of(int b, int x) { return ROW ? b : x; }
+  __device__ static __forceinline__ int col_of(int b, int x) { return ROW ? x : b; }
 };
 
 // Factorisation L = R0 * R1 used for each supported length.
@@ -251,22 +272,32 @@ template <int L, int BATCH, bool ROW, int W> struct Axis {
   static constexpr int NV = P0::NV > P1::NV ? P0::NV : P1::NV;
 };
 
+// f(e, row, col) for every input (for_inputs) / output (for_outputs) value
+// e of this thread in pass PS.
 template <class PS, class F> __device__ __forceinline__ void for_inputs(int t, F&& f) {
+  const typename PS::Lane l = PS::lane(t);
 #pragma unroll
   for (int s = 0; s < PS::NS; ++s) {
-    int b, i;
-    if (!PS::get(t, s, b, i)) continue;
+    if (!PS::active(l, t, s)) continue;
+    const int b = PS::b_of(l, s), i = PS::i_of(l, s);
 #pragma unroll
-    for (int r = 0; r < PS::R; ++r) f(s * PS::R + r, b, PS::in_x(i, r));
+    for (int r = 0; r < PS::R; ++r) {
+      const int x = PS::in_x(i, r);
+      f(s * PS::R + r, PS::row_of(b, x), PS::col_of(b, x));
+    }
   }
 }
 template <class PS, class F> __device__ __forceinline__ void for_outputs(int t, F&& f) {
+  const typename PS::Lane l = PS::lane(t);
 #pragma unroll
   for (int s = 0; s < PS::NS; ++s) {
-    int b, i;
-    if (!PS::get(t, s, b, i)) continue;
+    if (!PS::active(l, t, s)) continue;
+    const int b = PS::b_of(l, s), i = PS::i_of(l, s);
 #pragma unroll
-    for (int r = 0; r < PS::R; ++r) f(s * PS::R + r, b, PS::out_x(i, r));
+    for (int r = 0; r < PS::R; ++r) {
+      const int x = PS::out_x(i, r);
+      f(s * PS::R + r, PS::row_of(b, x), PS::col_of(b, x));
+    }
   }
 }
 
@@ -274,16 +305,14 @@ template <class PS, class F> __device__ __forceinline__ void for_outputs(int t, 
 // tw[m] = exp(-2 pi i m / L); DIR = -1 forward, +1 backward.
 template <class PS, int DIR, typename T>
 __device__ __forceinline__ void pass_compute(cx<T>* v, const cx<T>* tw, int t) {
+  const typename PS::Lane l = PS::lane(t);
 #pragma unroll
   for (int s = 0; s < PS::NS; ++s) {
     if constexpr (PS::P > 1) {
-      int b, i;
-      PS::get(t, s, b, i);
-      const int k = i % PS::P;
-      constexpr int STEP = PS::L / (PS::P * PS::R);
+      const int k = PS::i_of(l, s);  // k = i for the last pass of two
 #pragma unroll
       for (int r = 1; r < PS::R; ++r) {
-        cx<T> w = tw[r * k * STEP];
+        cx<T> w = tw[r * k];
         if constexpr (DIR > 0) w.y = -w.y;
         v[s * PS::R + r] = cmul<T>(v[s * PS::R + r], w);
       }
@@ -292,30 +321,35 @@ __device__ __forceinline__ void pass_compute(cx<T>* v, const cx<T>* tw, int t) {
   }
 }
 
-__device__ __forceinline__ int lds_pad(int p) { return p + (p >> 5); }
-constexpr int lds_slots(int n) { return n + (n >> 5) + 1; }
+// LDS tile of ROWS x COLS complex values with a padded row stride.
+template <int COLS> struct Tile {
+  static constexpr int SL = COLS + 1;
+  __device__ static __forceinline__ int at(int row, int col) { return row * SL + col; }
+  static constexpr int slots(int rows) { return rows * SL; }
+};
 
 // Move the outputs of pass A (in registers) to the inputs of pass B through
-// LDS.  SPLIT exchanges real and imaginary parts in two rounds so that an
-// FP64 tile needs only 8 bytes of LDS per element.
-template <class PA, class PB, bool SPLIT, typename T>
+// an LDS tile of COLS columns.  SPLIT exchanges real and imaginary parts in
+// two rounds so that an FP64 tile needs only 8 bytes of LDS per element.
+template <class PA, class PB, int COLS, bool SPLIT, typename T>
 __device__ __forceinline__ void exchange(cx<T>* v, void* smem, int t) {
+  using TL = Tile<COLS>;
   if constexpr (!SPLIT) {
     cx<T>* buf = reinterpret_cast<cx<T>*>(smem);
-    for_outputs<PA>(t, [&](int e, int b, int x) { buf[lds_pad(PA::pos(b, x))] = v[e]; });
+    for_outputs<PA>(t, [&](int e, int row, int col) { buf[TL::at(row, col)] = v[e]; });
     __syncthreads();
-    for_inputs<PB>(t, [&](int e, int b, int x) { v[e] = buf[lds_pad(PB::pos(b, x))]; });
+    for_inputs<PB>(t, [&](int e, int row, int col) { v[e] = buf[TL::at(row, col)]; });
     __syncthreads();
   } else {
     T* buf = reinterpret_cast<T*>(smem);
     T tmp[PB::NV];
-    for_outputs<PA>(t, [&](int e, int b, int x) { buf[lds_pad(PA::pos(b, x))] = v[e].x; });
+    for_outputs<PA>(t, [&](int e, int row, int col) { buf[TL::at(row, col)] = v[e].x; });
     __syncthreads();
-    for_inputs<PB>(t, [&](int e, int b, int x) { tmp[e] = buf[lds_pad(PB::pos(b, x))]; });
+    for_inputs<PB>(t, [&](int e, int row, int col) { tmp[e] = buf[TL::at(row, col)]; });
     __syncthreads();
-    for_outputs<PA>(t, [&](int e, int b, int x) { buf[lds_pad(PA::pos(b, x))] = v[e].y; });
+    for_outputs<PA>(t, [&](int e, int row, int col) { buf[TL::at(row, col)] = v[e].y; });
     __syncthreads();
-    for_inputs<PB>(t, [&](int e, int b, int x) { v[e] = mk<T>(tmp[e], buf[lds_pad(PB::pos(b, x))]); });
+    for_inputs<PB>(t, [&](int e, int row, int col) { v[e] = mk<T>(tmp[e], buf[TL::at(row, col)]); });
     __syncthreads();
   }
 }

@@ -59,6 +59,7 @@ struct PlaneArgs {
   int i0, j0, ti, tj;  // tile origin and extent
   int n1, nb;
   double fscale;       // constant factor on f in P3
+  int store_v;         // P3: also write the real-space v back into the pair buffer
 };
 
 struct PencilArgs {
@@ -102,42 +103,26 @@ __device__ __forceinline__ int signed_index(int i, int n) { return i < (n >> 1) 
 // ---------------------------------------------------------------------------
 // Plane kernel: 2-D FFT over (i2, i3) of one i1 plane.
 // ---------------------------------------------------------------------------
-template <int N2, int N3> struct PlaneShape;
-template <> struct PlaneShape<24, 24> { static constexpr int W = 128; };
-template <> struct PlaneShape<48, 48> { static constexpr int W = 256; };
-template <> struct PlaneShape<48, 64> { static constexpr int W = 128; };
-template <> struct PlaneShape<64, 64> { static constexpr int W = 256; };
-template <> struct PlaneShape<72, 72> { static constexpr int W = 576; };
-template <> struct PlaneShape<96, 96> { static constexpr int W = 384; };
-template <> struct PlaneShape<96, 128> { static constexpr int W = 512; };
 
-template <typename T, int N2, int N3> struct PlaneCfg {
-  static constexpr int W = PlaneShape<N2, N3>::W;
+// Plane body: W threads, SPLIT selects the 8-byte (two-round) LDS exchange.
+template <typename T, int N2, int N3, int W, bool SPLIT> struct PlaneGeom {
   static constexpr int PLANE = N2 * N3;
-  // FP64 tiles above 64 KB exchange real and imaginary parts separately.
-  static constexpr bool SPLIT = sizeof(T) == 8 && lds_slots(PLANE) * 16 > 65536;
-  static constexpr int XBYTES = lds_slots(PLANE) * (SPLIT ? (int)sizeof(T) : 2 * (int)sizeof(T));
+  static constexpr int XBYTES = Tile<N3>::slots(N2) * (SPLIT ? (int)sizeof(T) : 2 * (int)sizeof(T));
   using Rw = Axis<N3, N2, true, W>;   // transforms along i3, one per row
   using Cl = Axis<N2, N3, false, W>;  // transforms along i2, one per column
   static constexpr int NV = Rw::NV > Cl::NV ? Rw::NV : Cl::NV;
 };
 
-template <typename T, int N2, int N3, int MODE>
-__global__ __launch_bounds__((PlaneCfg<T, N2, N3>::W)) void plane_kernel(PlaneArgs A) {
-  using Cfg = PlaneCfg<T, N2, N3>;
-  using Rw = typename Cfg::Rw;
-  using Cl = typename Cfg::Cl;
-  constexpr bool SPLIT = Cfg::SPLIT;
+template <typename T, int N2, int N3, int W, bool SPLIT, int MODE>
+__device__ __forceinline__ void plane_body(const PlaneArgs& A, int lid, unsigned char* smem, const cx<T>* tw2,
+                                           const cx<T>* tw3) {
+  using Cfg = PlaneGeom<T, N2, N3, W, SPLIT>;
+  using R0 = typename Cfg::Rw::P0;
+  using R1 = typename Cfg::Rw::P1;
+  using C0 = typename Cfg::Cl::P0;
+  using C1 = typename Cfg::Cl::P1;
   constexpr int PLANE = Cfg::PLANE;
-  __shared__ __align__(16) unsigned char smem[Cfg::XBYTES];
-  __shared__ cx<T> tw2[N2];
-  __shared__ cx<T> tw3[N3];
-  load_table<T>(tw2, A.tw2, N2);
-  load_table<T>(tw3, A.tw3, N3);
-  __syncthreads();
-
   const int t = threadIdx.x;
-  const int lid = xcd_logical(blockIdx.x, gridDim.x);
   const long long N = A.N;
   cx<T> v[Cfg::NV];
 
@@ -147,134 +132,178 @@ __global__ __launch_bounds__((PlaneCfg<T, N2, N3>::W)) void plane_kernel(PlaneAr
     const int ii = rem / A.tj, jj = rem - ii * A.tj;
     const cx<T>* pa = reinterpret_cast<const cx<T>*>(A.a) + (long long)(A.i0 + ii) * N + (long long)i1 * PLANE;
     const cx<T>* pb = reinterpret_cast<const cx<T>*>(A.bsrc) + (long long)(A.j0 + jj) * N + (long long)i1 * PLANE;
-    for_inputs<typename Rw::P0>(t, [&](int e, int b, int x) {
-      const int p = Rw::P0::pos(b, x);
+    for_inputs<R0>(t, [&](int e, int row, int col) {
+      const int p = row * N3 + col;
       v[e] = cmulc<T>(pa[p], pb[p]);
     });
-    pass_compute<typename Rw::P0, -1, T>(v, tw3, t);
-    exchange<typename Rw::P0, typename Rw::P1, SPLIT, T>(v, smem, t);
-    pass_compute<typename Rw::P1, -1, T>(v, tw3, t);
-    exchange<typename Rw::P1, typename Cl::P0, SPLIT, T>(v, smem, t);
-    pass_compute<typename Cl::P0, -1, T>(v, tw2, t);
-    exchange<typename Cl::P0, typename Cl::P1, SPLIT, T>(v, smem, t);
-    pass_compute<typename Cl::P1, -1, T>(v, tw2, t);
+    pass_compute<R0, -1, T>(v, tw3, t);
+    exchange<R0, R1, N3, SPLIT, T>(v, smem, t);
+    pass_compute<R1, -1, T>(v, tw3, t);
+    exchange<R1, C0, N3, SPLIT, T>(v, smem, t);
+    pass_compute<C0, -1, T>(v, tw2, t);
+    exchange<C0, C1, N3, SPLIT, T>(v, smem, t);
+    pass_compute<C1, -1, T>(v, tw2, t);
     cx<T>* pw = reinterpret_cast<cx<T>*>(A.w) + (long long)(ii * A.tj + jj) * N + (long long)i1 * PLANE;
-    for_outputs<typename Cl::P1>(t, [&](int e, int b, int x) { pw[Cl::P1::pos(b, x)] = v[e]; });
+    for_outputs<C1>(t, [&](int e, int row, int col) { pw[row * N3 + col] = v[e]; });
   } else if constexpr (MODE == PLANE_INV_MAC) {
     const int i1 = lid / A.tj, jj = lid - (lid / A.tj) * A.tj;
-    cx<T> s[Rw::P1::NV];
+    cx<T> s[R1::NV];
 #pragma unroll
-    for (int e = 0; e < Rw::P1::NV; ++e) s[e] = mk<T>(T(0), T(0));
+    for (int e = 0; e < R1::NV; ++e) s[e] = mk<T>(T(0), T(0));
     for (int ii = 0; ii < A.ti; ++ii) {
       const cx<T>* pw = reinterpret_cast<const cx<T>*>(A.w) + (long long)(ii * A.tj + jj) * N + (long long)i1 * PLANE;
-      for_inputs<typename Cl::P0>(t, [&](int e, int b, int x) { v[e] = pw[Cl::P0::pos(b, x)]; });
-      pass_compute<typename Cl::P0, +1, T>(v, tw2, t);
-      exchange<typename Cl::P0, typename Cl::P1, SPLIT, T>(v, smem, t);
-      pass_compute<typename Cl::P1, +1, T>(v, tw2, t);
-      exchange<typename Cl::P1, typename Rw::P0, SPLIT, T>(v, smem, t);
-      pass_compute<typename Rw::P0, +1, T>(v, tw3, t);
-      exchange<typename Rw::P0, typename Rw::P1, SPLIT, T>(v, smem, t);
-      pass_compute<typename Rw::P1, +1, T>(v, tw3, t);
+      for_inputs<C0>(t, [&](int e, int row, int col) { v[e] = pw[row * N3 + col]; });
+      pass_compute<C0, +1, T>(v, tw2, t);
+      exchange<C0, C1, N3, SPLIT, T>(v, smem, t);
+      pass_compute<C1, +1, T>(v, tw2, t);
+      exchange<C1, R0, N3, SPLIT, T>(v, smem, t);
+      pass_compute<R0, +1, T>(v, tw3, t);
+      exchange<R0, R1, N3, SPLIT, T>(v, smem, t);
+      pass_compute<R1, +1, T>(v, tw3, t);
       const T fi = T(A.f[A.i0 + ii] * A.fscale);
       const cx<T>* pa = reinterpret_cast<const cx<T>*>(A.a) + (long long)(A.i0 + ii) * N + (long long)i1 * PLANE;
-      for_outputs<typename Rw::P1>(t, [&](int e, int b, int x) {
-        const cx<T> pr = cmul<T>(pa[Rw::P1::pos(b, x)], v[e]);
+      if (A.store_v) {
+        cx<T>* pv = const_cast<cx<T>*>(pw);
+        for_outputs<R1>(t, [&](int e, int row, int col) { pv[row * N3 + col] = v[e]; });
+      }
+      for_outputs<R1>(t, [&](int e, int row, int col) {
+        const cx<T> pr = cmul<T>(pa[row * N3 + col], v[e]);
         s[e] = mk<T>(s[e].x + fi * pr.x, s[e].y + fi * pr.y);
       });
     }
     cx<T>* pc = reinterpret_cast<cx<T>*>(A.acc) + (long long)jj * N + (long long)i1 * PLANE;
-    for_outputs<typename Rw::P1>(t, [&](int e, int b, int x) {
-      const int p = Rw::P1::pos(b, x);
+    for_outputs<R1>(t, [&](int e, int row, int col) {
+      const int p = row * N3 + col;
       pc[p] = cadd<T>(pc[p], s[e]);
     });
   } else if constexpr (MODE == PLANE_FWD) {
     const int ob = lid / A.n1, i1 = lid - (lid / A.n1) * A.n1;
     cx<T>* px = reinterpret_cast<cx<T>*>(A.x) + (long long)ob * N + (long long)i1 * PLANE;
-    for_inputs<typename Rw::P0>(t, [&](int e, int b, int x) { v[e] = px[Rw::P0::pos(b, x)]; });
-    pass_compute<typename Rw::P0, -1, T>(v, tw3, t);
-    exchange<typename Rw::P0, typename Rw::P1, SPLIT, T>(v, smem, t);
-    pass_compute<typename Rw::P1, -1, T>(v, tw3, t);
-    exchange<typename Rw::P1, typename Cl::P0, SPLIT, T>(v, smem, t);
-    pass_compute<typename Cl::P0, -1, T>(v, tw2, t);
-    exchange<typename Cl::P0, typename Cl::P1, SPLIT, T>(v, smem, t);
-    pass_compute<typename Cl::P1, -1, T>(v, tw2, t);
-    for_outputs<typename Cl::P1>(t, [&](int e, int b, int x) { px[Cl::P1::pos(b, x)] = v[e]; });
+    for_inputs<R0>(t, [&](int e, int row, int col) { v[e] = px[row * N3 + col]; });
+    pass_compute<R0, -1, T>(v, tw3, t);
+    exchange<R0, R1, N3, SPLIT, T>(v, smem, t);
+    pass_compute<R1, -1, T>(v, tw3, t);
+    exchange<R1, C0, N3, SPLIT, T>(v, smem, t);
+    pass_compute<C0, -1, T>(v, tw2, t);
+    exchange<C0, C1, N3, SPLIT, T>(v, smem, t);
+    pass_compute<C1, -1, T>(v, tw2, t);
+    for_outputs<C1>(t, [&](int e, int row, int col) { px[row * N3 + col] = v[e]; });
   } else {  // PLANE_INV
     const int ob = lid / A.n1, i1 = lid - (lid / A.n1) * A.n1;
     cx<T>* px = reinterpret_cast<cx<T>*>(A.x) + (long long)ob * N + (long long)i1 * PLANE;
-    for_inputs<typename Cl::P0>(t, [&](int e, int b, int x) { v[e] = px[Cl::P0::pos(b, x)]; });
-    pass_compute<typename Cl::P0, +1, T>(v, tw2, t);
-    exchange<typename Cl::P0, typename Cl::P1, SPLIT, T>(v, smem, t);
-    pass_compute<typename Cl::P1, +1, T>(v, tw2, t);
-    exchange<typename Cl::P1, typename Rw::P0, SPLIT, T>(v, smem, t);
-    pass_compute<typename Rw::P0, +1, T>(v, tw3, t);
-    exchange<typename Rw::P0, typename Rw::P1, SPLIT, T>(v, smem, t);
-    pass_compute<typename Rw::P1, +1, T>(v, tw3, t);
-    for_outputs<typename Rw::P1>(t, [&](int e, int b, int x) { px[Rw::P1::pos(b, x)] = v[e]; });
+    for_inputs<C0>(t, [&](int e, int row, int col) { v[e] = px[row * N3 + col]; });
+    pass_compute<C0, +1, T>(v, tw2, t);
+    exchange<C0, C1, N3, SPLIT, T>(v, smem, t);
+    pass_compute<C1, +1, T>(v, tw2, t);
+    exchange<C1, R0, N3, SPLIT, T>(v, smem, t);
+    pass_compute<R0, +1, T>(v, tw3, t);
+    exchange<R0, R1, N3, SPLIT, T>(v, smem, t);
+    pass_compute<R1, +1, T>(v, tw3, t);
+    for_outputs<R1>(t, [&](int e, int row, int col) { px[row * N3 + col] = v[e]; });
   }
+}
+
+// Default block shape per precision, plane and mode (measured on MI355X:
+// block size, LDS exchange width and occupancy hint of the fastest variant).
+struct PlaneTune {
+  int w;
+  bool split;
+  int minb;
+};
+constexpr PlaneTune plane_tune(int tbytes, int n2, int n3, int mode) {
+  const bool pair = mode == PLANE_PAIR_FWD, mac = mode == PLANE_INV_MAC;
+  if (tbytes == 8) {  // FP64
+    if (n2 == 64 && n3 == 64) return pair ? PlaneTune{512, true, 2} : mac ? PlaneTune{256, false, 2} : PlaneTune{256, true, 1};
+    if (n2 == 96 && n3 == 128) return pair ? PlaneTune{512, true, 1} : PlaneTune{1024, true, 1};
+    if (n2 == 96 && n3 == 96) return PlaneTune{768, true, 1};
+    if (n2 == 72 && n3 == 72) return PlaneTune{576, true, 1};
+    if (n2 == 48 && n3 == 64) return PlaneTune{256, false, 1};
+    if (n2 == 48 && n3 == 48) return PlaneTune{384, false, 1};
+    return PlaneTune{192, false, 1};
+  }
+  if (n2 == 96 && n3 == 128) return pair ? PlaneTune{512, true, 1} : PlaneTune{1024, false, 1};
+  if (n2 == 96 && n3 == 96) return mac ? PlaneTune{384, false, 1} : PlaneTune{768, false, 1};
+  if (n2 == 72 && n3 == 72) return PlaneTune{576, false, 1};
+  if (n2 == 64 && n3 == 64) return PlaneTune{512, false, 1};
+  if (n2 == 48 && n3 == 64) return PlaneTune{256, false, 1};
+  if (n2 == 48 && n3 == 48) return pair ? PlaneTune{192, false, 1} : PlaneTune{384, false, 1};
+  return PlaneTune{192, false, 1};
+}
+
+template <typename T, int N2, int N3, int MODE> struct PlaneCfg {
+  static constexpr PlaneTune P = plane_tune(sizeof(T), N2, N3, MODE);
+  static constexpr int W = P.w;
+  static constexpr bool SPLIT = P.split;
+  static constexpr int MINB = P.minb;
+};
+
+template <typename T, int N2, int N3, int W, bool SPLIT, int MODE, int MINB>
+__global__ __launch_bounds__(W, MINB) void plane_kernel(PlaneArgs A) {
+  using G = PlaneGeom<T, N2, N3, W, SPLIT>;
+  __shared__ __align__(16) unsigned char smem[G::XBYTES];
+  __shared__ cx<T> tw2[N2];
+  __shared__ cx<T> tw3[N3];
+  load_table<T>(tw2, A.tw2, N2);
+  load_table<T>(tw3, A.tw3, N3);
+  __syncthreads();
+  plane_body<T, N2, N3, W, SPLIT, MODE>(A, xcd_logical(blockIdx.x, gridDim.x), smem, tw2, tw3);
 }
 
 // ---------------------------------------------------------------------------
 // Pencil kernel: 1-D FFT along i1 for CB consecutive plane positions.
 // ---------------------------------------------------------------------------
-template <int N1> struct PencilShape;
-template <> struct PencilShape<24> { static constexpr int CB = 64, W = 128; };
-template <> struct PencilShape<48> { static constexpr int CB = 64, W = 128; };
-template <> struct PencilShape<64> { static constexpr int CB = 32, W = 256; };
-template <> struct PencilShape<72> { static constexpr int CB = 32, W = 256; };
-template <> struct PencilShape<96> { static constexpr int CB = 32, W = 128; };
-template <> struct PencilShape<128> { static constexpr int CB = 32, W = 256; };
+struct PencilTune {
+  int cb, w;
+};
+constexpr PencilTune pencil_tune(int tbytes, int n1) {
+  if (n1 == 24) return PencilTune{64, 128};
+  if (n1 == 48) return PencilTune{64, 128};
+  if (n1 == 64) return PencilTune{64, 256};
+  if (n1 == 72) return tbytes == 4 ? PencilTune{32, 128} : PencilTune{32, 256};
+  if (n1 == 96) return tbytes == 4 ? PencilTune{64, 512} : PencilTune{32, 256};
+  return PencilTune{32, 256};
+}
 
-template <typename T, int N1> struct PencilCfg {
-  static constexpr int CB = PencilShape<N1>::CB;
-  static constexpr int W = PencilShape<N1>::W;
-  static constexpr int TILE = N1 * CB;
-  static constexpr bool SPLIT = sizeof(T) == 8 && lds_slots(TILE) * 16 > 65536;
-  static constexpr int XBYTES = lds_slots(TILE) * (SPLIT ? (int)sizeof(T) : 2 * (int)sizeof(T));
+template <typename T, int N1, int CB, int W, bool SPLIT> struct PencilGeom {
+  static constexpr int XBYTES = Tile<CB>::slots(N1) * (SPLIT ? (int)sizeof(T) : 2 * (int)sizeof(T));
   using Ax = Axis<N1, CB, false, W>;
   static constexpr int NV = Ax::NV;
 };
 
-template <typename T, int N1, int MODE>
-__global__ __launch_bounds__((PencilCfg<T, N1>::W)) void pencil_kernel(PencilArgs A) {
-  using Cfg = PencilCfg<T, N1>;
+template <typename T, int N1, int CB, int W, bool SPLIT, int MODE>
+__device__ __forceinline__ void pencil_body(const PencilArgs& A, int lid, unsigned char* smem, const cx<T>* tw1,
+                                            double* red) {
+  using Cfg = PencilGeom<T, N1, CB, W, SPLIT>;
   using P0 = typename Cfg::Ax::P0;
   using P1 = typename Cfg::Ax::P1;
-  constexpr bool SPLIT = Cfg::SPLIT;
-  constexpr int CB = Cfg::CB;
-  __shared__ __align__(16) unsigned char smem[Cfg::XBYTES];
-  __shared__ cx<T> tw1[N1];
-  __shared__ double red[(Cfg::W + 63) / 64];
-  load_table<T>(tw1, A.tw1, N1);
-  __syncthreads();
-
   const int t = threadIdx.x;
   const int plane = A.n2 * A.n3;
   const int ngroups = plane / CB;
-  const int lid = xcd_logical(blockIdx.x, gridDim.x);
   const int pr = lid / ngroups, g = lid - (lid / ngroups) * ngroups;
   const int c0 = g * CB;
   cx<T>* base = reinterpret_cast<cx<T>*>(A.x) + (long long)pr * A.N + c0;
   cx<T> v[Cfg::NV];
 
+  // (row, col) of the tile = (i1, column c0 + col)
   constexpr int DIR0 = (MODE == PENCIL_INV) ? +1 : -1;
-  for_inputs<P0>(t, [&](int e, int b, int x) { v[e] = base[(long long)x * plane + b]; });
+  for_inputs<P0>(t, [&](int e, int row, int col) { v[e] = base[(long long)row * plane + col]; });
   pass_compute<P0, DIR0, T>(v, tw1, t);
-  exchange<P0, P1, SPLIT, T>(v, smem, t);
+  exchange<P0, P1, CB, SPLIT, T>(v, smem, t);
   pass_compute<P1, DIR0, T>(v, tw1, t);
 
   if constexpr (MODE == PENCIL_FWD || MODE == PENCIL_INV) {
-    for_outputs<P1>(t, [&](int e, int b, int x) { base[(long long)x * plane + b] = v[e]; });
+    for_outputs<P1>(t, [&](int e, int row, int col) { base[(long long)row * plane + col] = v[e]; });
     return;
   } else {
-    // Coulomb kernel on the natural-order outputs (b = column, x = k1).
+    // Coulomb kernel on the natural-order outputs (column c0 + b, k1 = row).
     const KernelParams& kp = A.kp;
     double esum = 0.0;
     const double k0 = kp.q_zero ? *kp.k0 : 0.0;
+    const typename P1::Lane l = P1::lane(t);
 #pragma unroll
     for (int s = 0; s < P1::NS; ++s) {
-      int b, i;
-      const bool act = P1::get(t, s, b, i);
+      const int b = P1::b_of(l, s), i = P1::i_of(l, s);
+      const bool act = P1::active(l, t, s);
       const int c = c0 + b;
       const int m2 = signed_index(c / A.n3, A.n2);
       const int m3 = signed_index(c - (c / A.n3) * A.n3, A.n3);
@@ -315,12 +344,58 @@ __global__ __launch_bounds__((PencilCfg<T, N1>::W)) void pencil_kernel(PencilArg
       if (t == 0) A.epart[(long long)pr * ngroups + g] = tot;
     }
     if constexpr (MODE == PENCIL_FKI) {
-      exchange<P1, P0, SPLIT, T>(v, smem, t);
+      exchange<P1, P0, CB, SPLIT, T>(v, smem, t);
       pass_compute<P0, +1, T>(v, tw1, t);
-      exchange<P0, P1, SPLIT, T>(v, smem, t);
+      exchange<P0, P1, CB, SPLIT, T>(v, smem, t);
       pass_compute<P1, +1, T>(v, tw1, t);
-      for_outputs<P1>(t, [&](int e, int b, int x) { base[(long long)x * plane + b] = v[e]; });
+      for_outputs<P1>(t, [&](int e, int row, int col) { base[(long long)row * plane + col] = v[e]; });
     }
+  }
+}
+
+template <typename T, int N1, int MODE> struct PencilCfg {
+  static constexpr int CB = pencil_tune(sizeof(T), N1).cb;
+  static constexpr int W = pencil_tune(sizeof(T), N1).w;
+  static constexpr bool SPLIT = sizeof(T) == 8 && Tile<CB>::slots(N1) * 16 > 65536;
+};
+
+template <typename T, int N1, int CB, int W, bool SPLIT, int MODE, int MINB>
+__global__ __launch_bounds__(W, MINB) void pencil_kernel(PencilArgs A) {
+  using G = PencilGeom<T, N1, CB, W, SPLIT>;
+  __shared__ __align__(16) unsigned char smem[G::XBYTES];
+  __shared__ cx<T> tw1[N1];
+  __shared__ double red[(W + 63) / 64];
+  load_table<T>(tw1, A.tw1, N1);
+  __syncthreads();
+  pencil_body<T, N1, CB, W, SPLIT, MODE>(A, xcd_logical(blockIdx.x, gridDim.x), smem, tw1, red);
+}
+
+// ---------------------------------------------------------------------------
+// Mirrored accumulation of the pair-symmetric schedule (q = 0, one block of
+// orbitals): v_ji = conj(v_ij) in real space, so for a pair tile whose
+// real-space v_ij is in the pair buffer,
+//   acc_i += sum_j f_j phi_j conj(v_ij)
+// One block per (ii, i1); pure streaming, no transform.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void mac_conj_kernel(PlaneArgs A, int plane) {
+  const int lid = xcd_logical(blockIdx.x, gridDim.x);
+  const int i1 = lid / A.ti, ii = lid - (lid / A.ti) * A.ti;
+  const long long N = A.N;
+  const long long off = (long long)i1 * plane;
+  const cx<T>* w = reinterpret_cast<const cx<T>*>(A.w) + (long long)(ii * A.tj) * N + off;
+  const cx<T>* pb = reinterpret_cast<const cx<T>*>(A.bsrc) + (long long)A.j0 * N + off;
+  cx<T>* pc = reinterpret_cast<cx<T>*>(A.acc) + (long long)ii * N + off;
+  for (int p = threadIdx.x; p < plane; p += 256) {
+    T sx = T(0), sy = T(0);
+    for (int jj = 0; jj < A.tj; ++jj) {
+      const T fj = T(A.f[A.j0 + jj] * A.fscale);
+      const cx<T> z = cmulc<T>(w[(long long)jj * N + p], pb[(long long)jj * N + p]);  // conj(v) * phi_j
+      sx += fj * z.x;
+      sy += fj * z.y;
+    }
+    const cx<T> c = pc[p];
+    pc[p] = mk<T>(c.x + sx, c.y + sy);
   }
 }
 

@@ -9,11 +9,12 @@ namespace fockx {
 
 bool plane_supported(int n2, int n3);
 bool pencil_supported(int n1);
-int pencil_columns(int n1);  // columns per pencil workgroup
+int pencil_columns(int n1, int tbytes);  // columns per pencil workgroup
 
 template <typename T> hipError_t launch_plane(int mode, int n2, int n3, const PlaneArgs& a, int nblocks, hipStream_t s);
 template <typename T> hipError_t launch_pencil(int mode, int n1, const PencilArgs& a, int nblocks, hipStream_t s);
 template <typename T> hipError_t launch_zero(void* p, long long n, hipStream_t s);
+template <typename T> hipError_t launch_mac_conj(const PlaneArgs& a, int plane, int nblocks, hipStream_t s);
 template <typename T>
 hipError_t launch_scatter(const void* c, int ldc, const int* slot, int npw, int nb, void* box, long long N, hipStream_t s);
 template <typename T>
@@ -21,7 +22,7 @@ hipError_t launch_gather(const void* box, long long N, const int* slot, int npw,
                          const double* w, int j0, const double* g, hipStream_t s);
 
 hipError_t launch_energy_tile(const double* epart, int ngroups, const double* f, const double* g, int i0, int j0, int ti,
-                              int tj, const unsigned char* mask, double* tile_e, hipStream_t s);
+                              int tj, int sym, double* tile_e, hipStream_t s);
 hipError_t launch_energy_final(const double* tile_e, int ntiles, double scale, double* ex, hipStream_t s);
 hipError_t launch_gb(const KernelParams& kp, const int n[3], const int nq[3], double alpha, double head,
                      double* partial, int nparts, double* k0, hipStream_t s);

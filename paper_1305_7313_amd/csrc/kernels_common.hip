@@ -4,18 +4,26 @@
 namespace fockx {
 
 // Per tile: sum_{pairs} f_i g_j sum_groups epart -> tile_e[tile]   (one block, fixed order)
+// sym: the tile stands for both orders of each pair (one orbital block, q = 0,
+// sum_G K |rho_ji|^2 = sum_G K |rho_ij|^2): weight f_i g_j + f_j g_i, and in a
+// diagonal tile (i0 == j0) only ii < jj counts twice, ii == jj once.
 __global__ void energy_tile_kernel(const double* __restrict__ epart, int ngroups, const double* __restrict__ f,
-                                   const double* __restrict__ g, int i0, int j0, int ti, int tj,
-                                   const unsigned char* __restrict__ pair_mask, double* __restrict__ tile_e) {
+                                   const double* __restrict__ g, int i0, int j0, int ti, int tj, int sym,
+                                   double* __restrict__ tile_e) {
   __shared__ double red[16];
   double acc = 0.0;
   for (int pr = threadIdx.x; pr < ti * tj; pr += blockDim.x) {
     const int ii = pr / tj, jj = pr - (pr / tj) * tj;
+    const int i = i0 + ii, j = j0 + jj;
+    double wgt = f[i] * g[j];
+    if (sym) {
+      if (i0 == j0) wgt = ii < jj ? wgt + f[j] * g[i] : (ii == jj ? wgt : 0.0);
+      else wgt += f[j] * g[i];
+    }
+    if (wgt == 0.0) continue;
     double s = 0.0;
     const double* e = epart + (long long)pr * ngroups;
     for (int k = 0; k < ngroups; ++k) s += e[k];
-    double wgt = f[i0 + ii] * g[j0 + jj];
-    if (pair_mask) wgt *= double(pair_mask[pr]);
     acc += wgt * s;
   }
   const double tot = block_sum(acc, red);
@@ -78,21 +86,14 @@ bool plane_supported(int n2, int n3) {
 bool pencil_supported(int n1) {
   return n1 == 24 || n1 == 48 || n1 == 64 || n1 == 72 || n1 == 96 || n1 == 128;
 }
-int pencil_columns(int n1) {
-  switch (n1) {
-    case 24: return PencilShape<24>::CB;
-    case 48: return PencilShape<48>::CB;
-    case 64: return PencilShape<64>::CB;
-    case 72: return PencilShape<72>::CB;
-    case 96: return PencilShape<96>::CB;
-    case 128: return PencilShape<128>::CB;
-  }
-  return 0;
+int pencil_columns(int n1, int tbytes) {
+  if (!pencil_supported(n1)) return 0;
+  return pencil_tune(tbytes, n1).cb;
 }
 
 hipError_t launch_energy_tile(const double* epart, int ngroups, const double* f, const double* g, int i0, int j0,
-                              int ti, int tj, const unsigned char* mask, double* tile_e, hipStream_t s) {
-  hipLaunchKernelGGL(energy_tile_kernel, dim3(1), dim3(256), 0, s, epart, ngroups, f, g, i0, j0, ti, tj, mask,
+                              int ti, int tj, int sym, double* tile_e, hipStream_t s) {
+  hipLaunchKernelGGL(energy_tile_kernel, dim3(1), dim3(256), 0, s, epart, ngroups, f, g, i0, j0, ti, tj, sym,
                      tile_e);
   return hipGetLastError();
 }

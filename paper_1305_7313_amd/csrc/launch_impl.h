@@ -7,7 +7,8 @@ namespace {
 template <int MODE, int N2, int N3>
 hipError_t plane_go(const PlaneArgs& a, int nblocks, hipStream_t s) {
   using T = FX_T;
-  hipLaunchKernelGGL((plane_kernel<T, N2, N3, MODE>), dim3(nblocks), dim3(PlaneCfg<T, N2, N3>::W), 0, s, a);
+  using C = PlaneCfg<T, N2, N3, MODE>;
+  hipLaunchKernelGGL((plane_kernel<T, N2, N3, C::W, C::SPLIT, MODE, C::MINB>), dim3(nblocks), dim3(C::W), 0, s, a);
   return hipGetLastError();
 }
 template <int N2, int N3>
@@ -23,7 +24,8 @@ hipError_t plane_mode(int mode, const PlaneArgs& a, int nblocks, hipStream_t s) 
 template <int MODE, int N1>
 hipError_t pencil_go(const PencilArgs& a, int nblocks, hipStream_t s) {
   using T = FX_T;
-  hipLaunchKernelGGL((pencil_kernel<T, N1, MODE>), dim3(nblocks), dim3(PencilCfg<T, N1>::W), 0, s, a);
+  using C = PencilCfg<T, N1, MODE>;
+  hipLaunchKernelGGL((pencil_kernel<T, N1, C::CB, C::W, C::SPLIT, MODE, 1>), dim3(nblocks), dim3(C::W), 0, s, a);
   return hipGetLastError();
 }
 template <int N1>
@@ -64,6 +66,12 @@ hipError_t launch_pencil<FX_T>(int mode, int n1, const PencilArgs& a, int nblock
     case 128: return pencil_mode<128>(mode, a, nblocks, s);
   }
   return hipErrorInvalidValue;
+}
+
+template <>
+hipError_t launch_mac_conj<FX_T>(const PlaneArgs& a, int plane, int nblocks, hipStream_t s) {
+  hipLaunchKernelGGL(mac_conj_kernel<FX_T>, dim3(nblocks), dim3(256), 0, s, a, plane);
+  return hipGetLastError();
 }
 
 template <>

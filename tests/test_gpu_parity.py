@@ -81,6 +81,11 @@ CASES = {
     "ragged_gb": dict(a=synth.cubic_cell(10.0), n=(24, 24, 24), nocc=17, ntgt=5, q=(0.0, 0.0, 0.0), g0=1),
     "skew_q": dict(a=np.array([[10.0, 0.0, 0.0], [1.0, 18.0, 0.0], [0.5, 0.3, 24.0]]), n=(24, 48, 64),
                    nocc=6, ntgt=7, q=(0.03, 0.02, -0.04), g0=0),
+    # one block applied to itself at q = 0: the pair-symmetric schedule (3 tiles, ragged)
+    "self_ragged": dict(a=synth.cubic_cell(10.0), n=(24, 24, 24), nocc=37, ntgt=37, q=(0.0, 0.0, 0.0), g0=0,
+                        self=True),
+    "self_gb_skew": dict(a=np.array([[10.0, 0.0, 0.0], [1.0, 18.0, 0.0], [0.5, 0.3, 24.0]]), n=(24, 48, 64),
+                         nocc=20, ntgt=20, q=(0.0, 0.0, 0.0), g0=1, self=True),
 }
 
 
@@ -89,7 +94,7 @@ def case(request):
     c = CASES[request.param]
     s = synth.make_system(c["a"], c["n"])
     occ = synth.random_orbitals(s.a, s.miller, c["nocc"], 3)
-    tgt = synth.random_orbitals(s.a, s.miller, c["ntgt"], 4)
+    tgt = occ if c.get("self") else synth.random_orbitals(s.a, s.miller, c["ntgt"], 4)
     rng = np.random.default_rng(9)
     f = rng.uniform(0.2, 1.0, c["nocc"])
     g = rng.uniform(0.2, 1.0, c["ntgt"])
@@ -108,12 +113,13 @@ def test_cases_apply_energy_grad(case, prec):
     name, c, s, occ, tgt, f, g, q, v_ref, e_ref, go_ref, gt_ref = case
     print(f"[case] {name} {prec}", flush=True)
     cell = F.Cell(s.a, s.n, s.miller, g0=c["g0"], gb_alpha=0.7, nq=(2, 2, 2))
-    co, ct = dev(occ, _ctype(prec)), dev(tgt, _ctype(prec))
+    co = dev(occ, _ctype(prec))
+    ct = co if c.get("self") else dev(tgt, _ctype(prec))
     fd, gd = dev(f), dev(g)
     v = host(F.fock_apply(cell, q, co, fd, ct))
     e = float(host(F.fock_energy(cell, q, co, fd, ct, gd)))
     one = torch.ones((), dtype=torch.float64, device="cuda")
-    go, gt = torch.empty_like(co), torch.empty_like(ct)
+    go, gt = torch.empty_like(co), torch.empty_like(co if c.get("self") else ct)
     F.fock_energy_backward(cell, q, co, fd, ct, gd, one, go, gt)
     errs = dict(apply_rel=rel_fro(v, v_ref), apply_maxband=max_row_rel(v, v_ref),
                 E_rel=abs(e - e_ref) / abs(e_ref), gocc_rel=rel_fro(host(go), go_ref),
