@@ -4,6 +4,7 @@
 
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -35,7 +36,7 @@ enum KClass : int {
 };
 const char* const kClassNames[KC_COUNT] = {
     "a1_scatter", "a1_pencil_inv", "a1_plane_inv", "p1_pair_plane_fwd", "p2_pencil_kernel",
-    "p2_pencil_energy", "p3_plane_inv_mac", "p3_mirror_mac", "a7_plane_fwd", "a7_pencil_fwd", "a7_gather",
+    "p2_pencil_energy", "p3_plane_inv_mac", "p3_pair_mac", "a7_plane_fwd", "a7_pencil_fwd", "a7_gather",
     "reduce", "zero_fill"};
 
 struct Tracer {
@@ -451,6 +452,18 @@ struct Engine {
     return FOCK_OK;
   }
 
+  // Symmetric-schedule variant: 0 = fused inverse FFT + MAC with the mirrored
+  // half streamed afterwards (less VALU-parallel, fewer kernel phases; best
+  // for FP64), 1 = fully parallel inverse FFT then one MAC for both halves
+  // (best for FP32, whose transforms are VALU-bound).  FOCK_SYM_SCHEDULE
+  // overrides the default.
+  static int sym_schedule() {
+    const char* e = std::getenv("FOCK_SYM_SCHEDULE");
+    const int env = e ? std::atoi(e) : -1;
+    if (env == 0 || env == 1) return env;
+    return sizeof(T) == 8 ? 0 : 1;
+  }
+
   // The band-pair loop.  energy == false: apply -> out; true: energy partials -> tile_e.
   // sym: one orbital block at q = 0; only tiles I <= J are transformed, and
   // v_ji = conj(v_ij) supplies the mirrored pairs.
@@ -490,7 +503,7 @@ struct Engine {
       return FOCK_OK;
     }
     // symmetric schedule: accumulators for every orbital live in the (unused) phiB region
-    const int T0 = t.ti;
+    const int T0 = t.ti < kMacTile ? t.ti : kMacTile;
     void* acc_all = ws + L.phiB;
     if (!energy) {
       FX_TRACE(KC_ZERO);
@@ -500,26 +513,52 @@ struct Engine {
       const int tj = (nB - j0) < T0 ? (nB - j0) : T0;
       for (int i0 = 0; i0 <= j0; i0 += T0, ++tile) {
         const int ti = (nA - i0) < T0 ? (nA - i0) : T0;
-        char* accJ = static_cast<char*>(acc_all) + (size_t)j0 * P.N * sizeof(cx<T>);
-        PlaneArgs la = plane_args(phiA, phiA, w, accJ, fA, i0, j0, ti, tj);
+        PlaneArgs la = plane_args(phiA, phiA, w, nullptr, fA, i0, j0, ti, tj);
         if ((st = tile_forward(la, kp, energy, epart)) != FOCK_OK) return st;
         if (energy) {
           FX_TRACE(KC_REDUCE);
           FX_HIP(launch_energy_tile(epart, ngroups, fA, gB, i0, j0, ti, tj, 1, tile_e + tile, s));
           continue;
         }
-        la.store_v = i0 != j0;
+        if (sym_schedule() == 0) {
+          // fused inverse plane FFT + multiply-accumulate into acc_J; off-diagonal
+          // tiles leave v_ij in real space for the mirrored half.
+          PlaneArgs lp = la;
+          lp.acc = static_cast<char*>(acc_all) + (size_t)j0 * P.N * sizeof(cx<T>);
+          lp.store_v = i0 != j0;
+          {
+            FX_TRACE(KC_P3);
+            FX_HIP(launch_plane<T>(PLANE_INV_MAC, P.n[1], P.n[2], lp, tj * P.n[0], s));
+          }
+          if (i0 != j0) {
+            PlaneArgs lb = lp;
+            lb.acc = static_cast<char*>(acc_all) + (size_t)i0 * P.N * sizeof(cx<T>);
+            FX_TRACE(KC_P3B);
+            FX_HIP(launch_mac_conj<T>(lb, P.n[1] * P.n[2], ti * P.n[0], s));
+          }
+          continue;
+        }
         {
+          // inverse plane FFT of every pair of the tile, in place: v_ij in real space
           FX_TRACE(KC_P3);
-          FX_HIP(launch_plane<T>(PLANE_INV_MAC, P.n[1], P.n[2], la, tj * P.n[0], s));
+          PlaneArgs lv = plane_args(nullptr, nullptr, nullptr, nullptr, nullptr, 0, 0, 0, 0);
+          lv.x = w;
+          lv.nb = ti * tj;
+          FX_HIP(launch_plane<T>(PLANE_INV, P.n[1], P.n[2], lv, ti * tj * P.n[0], s));
         }
-        if (i0 != j0) {
-          // acc_i += sum_j f_j phi_j conj(v_ij)
-          PlaneArgs lb = la;
-          lb.acc = static_cast<char*>(acc_all) + (size_t)i0 * P.N * sizeof(cx<T>);
-          FX_TRACE(KC_P3B);
-          FX_HIP(launch_mac_conj<T>(lb, P.n[1] * P.n[2], ti * P.n[0], s));
-        }
+        MacArgs ma{};
+        ma.w = w;
+        ma.phi = phiA;
+        ma.f = fA;
+        ma.acc = acc_all;
+        ma.N = P.N;
+        ma.i0 = i0;
+        ma.j0 = j0;
+        ma.ti = ti;
+        ma.tj = tj;
+        ma.mirror = i0 != j0;
+        FX_TRACE(KC_P3B);
+        FX_HIP(launch_mac_pair<T>(ma, s));
       }
     }
     if (!energy && (st = finish(acc_all, nB, 0, out, ldo, s0, wout, gscale)) != FOCK_OK) return st;

@@ -211,7 +211,7 @@ struct PlaneTune {
   int minb;
 };
 constexpr PlaneTune plane_tune(int tbytes, int n2, int n3, int mode) {
-  const bool pair = mode == PLANE_PAIR_FWD, mac = mode == PLANE_INV_MAC;
+  const bool pair = mode == PLANE_PAIR_FWD || mode == PLANE_INV, mac = mode == PLANE_INV_MAC;
   if (tbytes == 8) {  // FP64
     if (n2 == 64 && n3 == 64) return pair ? PlaneTune{512, true, 2} : mac ? PlaneTune{256, false, 2} : PlaneTune{256, true, 1};
     if (n2 == 96 && n3 == 128) return pair ? PlaneTune{512, true, 1} : PlaneTune{1024, true, 1};
@@ -371,31 +371,97 @@ __global__ __launch_bounds__(W, MINB) void pencil_kernel(PencilArgs A) {
 }
 
 // ---------------------------------------------------------------------------
-// Mirrored accumulation of the pair-symmetric schedule (q = 0, one block of
-// orbitals): v_ji = conj(v_ij) in real space, so for a pair tile whose
-// real-space v_ij is in the pair buffer,
-//   acc_i += sum_j f_j phi_j conj(v_ij)
-// One block per (ii, i1); pure streaming, no transform.
+// Multiply-accumulate of the pair-symmetric schedule (q = 0, one orbital
+// block).  The pair buffer holds v_ij in real space for a tile (i in I,
+// j in J); since v_ji = conj(v_ij),
+//   acc_j += sum_i f_i phi_i v_ij                 (every tile)
+//   acc_i += sum_j f_j phi_j conj(v_ij)           (off-diagonal tiles only)
+// Every grid point is independent: one thread per point, the tile's pairs
+// in registers, each pair value read once.
 // ---------------------------------------------------------------------------
+struct MacArgs {
+  const void* w;       // pair buffer [ti*tj][N], slot ii*tj + jj, real space
+  const void* phi;     // orbitals in real space [n][N]
+  const double* f;     // occupations
+  void* acc;           // accumulators [n][N]
+  long long N;
+  int i0, j0, ti, tj, mirror;
+};
+
+constexpr int kMacTile = 16;
+
+template <typename T>
+__global__ __launch_bounds__(256) void mac_pair_kernel(MacArgs A) {
+  const long long N = A.N;
+  const long long p = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (p >= N) return;
+  const cx<T>* __restrict__ w = reinterpret_cast<const cx<T>*>(A.w) + p;
+  const cx<T>* __restrict__ phi = reinterpret_cast<const cx<T>*>(A.phi) + p;
+  cx<T>* __restrict__ acc = reinterpret_cast<cx<T>*>(A.acc) + p;
+  const double* __restrict__ f = A.f;
+  const int ti = A.ti, tj = A.tj, mirror = A.mirror;
+  cx<T> fphi_i[kMacTile], acc_i[kMacTile];
+#pragma unroll
+  for (int ii = 0; ii < kMacTile; ++ii) {
+    if (ii < ti) fphi_i[ii] = cscale<T>(phi[(long long)(A.i0 + ii) * N], T(f[A.i0 + ii]));
+    acc_i[ii] = mk<T>(T(0), T(0));
+  }
+  for (int jj = 0; jj < tj; ++jj) {
+    const long long oj = (long long)(A.j0 + jj) * N;
+    const cx<T> aj0 = acc[oj];
+    const cx<T> fphi_j = cscale<T>(phi[oj], T(f[A.j0 + jj]));
+    cx<T> v[kMacTile];
+#pragma unroll
+    for (int ii = 0; ii < kMacTile; ++ii)
+      if (ii < ti) v[ii] = w[(long long)(ii * tj + jj) * N];
+    T sx = aj0.x, sy = aj0.y;
+#pragma unroll
+    for (int ii = 0; ii < kMacTile; ++ii) {
+      if (ii < ti) {
+        const cx<T> a = cmul<T>(fphi_i[ii], v[ii]);
+        sx += a.x;
+        sy += a.y;
+        if (mirror) {
+          const cx<T> m = cmulc<T>(v[ii], fphi_j);  // conj(v) f_j phi_j
+          acc_i[ii] = mk<T>(acc_i[ii].x + m.x, acc_i[ii].y + m.y);
+        }
+      }
+    }
+    acc[oj] = mk<T>(sx, sy);
+  }
+  if (mirror) {
+#pragma unroll
+    for (int ii = 0; ii < kMacTile; ++ii) {
+      if (ii < ti) {
+        const long long oi = (long long)(A.i0 + ii) * N;
+        const cx<T> c = acc[oi];
+        acc[oi] = mk<T>(c.x + acc_i[ii].x, c.y + acc_i[ii].y);
+      }
+    }
+  }
+}
+
+// Mirror half only (schedule with a fused P3 that left v_ij in the pair
+// buffer): acc_i += sum_j f_j phi_j conj(v_ij).  One block per (ii, i1).
 template <typename T>
 __global__ __launch_bounds__(256) void mac_conj_kernel(PlaneArgs A, int plane) {
   const int lid = xcd_logical(blockIdx.x, gridDim.x);
   const int i1 = lid / A.ti, ii = lid - (lid / A.ti) * A.ti;
   const long long N = A.N;
   const long long off = (long long)i1 * plane;
-  const cx<T>* w = reinterpret_cast<const cx<T>*>(A.w) + (long long)(ii * A.tj) * N + off;
-  const cx<T>* pb = reinterpret_cast<const cx<T>*>(A.bsrc) + (long long)A.j0 * N + off;
-  cx<T>* pc = reinterpret_cast<cx<T>*>(A.acc) + (long long)ii * N + off;
+  const cx<T>* __restrict__ w = reinterpret_cast<const cx<T>*>(A.w) + (long long)(ii * A.tj) * N + off;
+  const cx<T>* __restrict__ pb = reinterpret_cast<const cx<T>*>(A.bsrc) + (long long)A.j0 * N + off;
+  cx<T>* __restrict__ pc = reinterpret_cast<cx<T>*>(A.acc) + (long long)ii * N + off;
   for (int p = threadIdx.x; p < plane; p += 256) {
-    T sx = T(0), sy = T(0);
+    const cx<T> c = pc[p];
+    T sx = c.x, sy = c.y;
     for (int jj = 0; jj < A.tj; ++jj) {
       const T fj = T(A.f[A.j0 + jj] * A.fscale);
       const cx<T> z = cmulc<T>(w[(long long)jj * N + p], pb[(long long)jj * N + p]);  // conj(v) * phi_j
       sx += fj * z.x;
       sy += fj * z.y;
     }
-    const cx<T> c = pc[p];
-    pc[p] = mk<T>(c.x + sx, c.y + sy);
+    pc[p] = mk<T>(sx, sy);
   }
 }
 

@@ -14,6 +14,7 @@ int pencil_columns(int n1, int tbytes);  // columns per pencil workgroup
 template <typename T> hipError_t launch_plane(int mode, int n2, int n3, const PlaneArgs& a, int nblocks, hipStream_t s);
 template <typename T> hipError_t launch_pencil(int mode, int n1, const PencilArgs& a, int nblocks, hipStream_t s);
 template <typename T> hipError_t launch_zero(void* p, long long n, hipStream_t s);
+template <typename T> hipError_t launch_mac_pair(const MacArgs& a, hipStream_t s);
 template <typename T> hipError_t launch_mac_conj(const PlaneArgs& a, int plane, int nblocks, hipStream_t s);
 template <typename T>
 hipError_t launch_scatter(const void* c, int ldc, const int* slot, int npw, int nb, void* box, long long N, hipStream_t s);

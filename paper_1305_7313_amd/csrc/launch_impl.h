@@ -75,6 +75,13 @@ hipError_t launch_mac_conj<FX_T>(const PlaneArgs& a, int plane, int nblocks, hip
 }
 
 template <>
+hipError_t launch_mac_pair<FX_T>(const MacArgs& a, hipStream_t s) {
+  const long long blocks = (a.N + 255) / 256;
+  hipLaunchKernelGGL(mac_pair_kernel<FX_T>, dim3((unsigned)blocks), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+template <>
 hipError_t launch_zero<FX_T>(void* p, long long n, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   long long blocks = (n + 255) / 256;

@@ -107,11 +107,15 @@ def case(request):
 
 
 @pytest.mark.parametrize("prec", ["c128", "c64"])
-def test_cases_apply_energy_grad(case, prec):
+@pytest.mark.parametrize("schedule", ["0", "1"])
+def test_cases_apply_energy_grad(case, prec, schedule, monkeypatch):
     import torch
     F = _F()
     name, c, s, occ, tgt, f, g, q, v_ref, e_ref, go_ref, gt_ref = case
-    print(f"[case] {name} {prec}", flush=True)
+    if schedule == "1" and not c.get("self"):
+        pytest.skip("the schedule choice only exists for one block at q = 0")
+    monkeypatch.setenv("FOCK_SYM_SCHEDULE", schedule)
+    print(f"[case] {name} {prec} schedule={schedule}", flush=True)
     cell = F.Cell(s.a, s.n, s.miller, g0=c["g0"], gb_alpha=0.7, nq=(2, 2, 2))
     co = dev(occ, _ctype(prec))
     ct = co if c.get("self") else dev(tgt, _ctype(prec))
@@ -124,7 +128,7 @@ def test_cases_apply_energy_grad(case, prec):
     errs = dict(apply_rel=rel_fro(v, v_ref), apply_maxband=max_row_rel(v, v_ref),
                 E_rel=abs(e - e_ref) / abs(e_ref), gocc_rel=rel_fro(host(go), go_ref),
                 gtgt_rel=rel_fro(host(gt), gt_ref))
-    report(f"{name} {prec}", **errs)
+    report(f"{name} {prec} schedule={schedule}", **errs)
     for k, val in errs.items():
         assert val < TOL[prec], (k, val)
 
