@@ -109,6 +109,26 @@ fock_status fock_energy_backward(const fock_cell *cell, const double q[3], int32
                                  const fock_orbs *tgt, const double *grad_ex, void *grad_occ, void *grad_tgt,
                                  void *ws, size_t ws_bytes, void *stream);
 
+/* Exchange energy over a k-point mesh (section 4: the sums over k and q).
+ * sets[k] holds the orbitals at Bloch vector kpts[k] (host [nk][3], bohr^-1),
+ * all on the cell's sphere; sets[k].w are the weights (occupation / N_k for a
+ * uniform mesh).  Block (k, k') pairs targets at k with occupied orbitals at
+ * k', q = k - k' (not folded: the kernel uses |q + G|^2 directly):
+ *   E = -1/2 sum_{k,k'} sum_ij w_ik' w_jk Omega sum_G K(k - k' + G) |rho_{ik',jk}(G)|^2.
+ * The divergent term (k = k', G = 0) follows cell->g0 (the Gygi-Baldereschi
+ * constant of cell->nq, cell->gb_alpha).  Since E_kk' = E_k'k only k <= k' is
+ * evaluated.  Device FP64 scalar out.  Workspace: fock_workspace_size_kmesh. */
+size_t fock_workspace_size_kmesh(const fock_cell *cell, int32_t dtype, int32_t nk, int32_t nb_max);
+fock_status fock_energy_kmesh(const fock_cell *cell, int32_t nk, const double *kpts, int32_t dtype,
+                              const fock_orbs *sets, double *ex_out, void *ws, size_t ws_bytes, void *stream);
+/* Gradient of fock_energy_kmesh, scaled by the device scalar *grad_ex:
+ * grad[k][j] = grad_ex * dE/d conj(c_jk) = grad_ex * w_jk * sum_k' (V_x psi_jk)
+ * where V_x uses the occupied set k' and q = k - k'.  grad is a host array of
+ * nk device pointers ([nb_k][ld_k] each; a NULL entry skips that set). */
+fock_status fock_energy_kmesh_backward(const fock_cell *cell, int32_t nk, const double *kpts, int32_t dtype,
+                                       const fock_orbs *sets, const double *grad_ex, void *const *grad, void *ws,
+                                       size_t ws_bytes, void *stream);
+
 /* Auxiliary: unnormalised 3-D transform of nb boxes in place (device
  * [nb][n1][n2][n3] complex of dtype); sign = -1 forward (sum e^{-iG.r}),
  * +1 backward.  The same transforms the band-pair path uses; exposed so

@@ -234,3 +234,38 @@ def fock_energy_grad(a, n, miller, q, c_occ, f_occ, c_tgt, g_tgt, ecut_fock: flo
     vt = fock_apply(a, n, miller, q, c_occ, f_occ, c_tgt, ecut_fock, k0, method)
     vo = fock_apply(a, n, miller, -q, c_tgt, g_tgt, c_occ, ecut_fock, k0, method)
     return 0.5 * f_occ[:, None] * vo, 0.5 * g_tgt[:, None] * vt
+
+
+# --------------------------------------------------------------------------
+# k-point mesh (section 4: the sums over k and q)
+# --------------------------------------------------------------------------
+
+def fock_energy_kmesh(a, n, miller, kpts, sets, weights, ecut_fock: float = 0.0, k0: float = 0.0,
+                      method: str = "auto") -> float:
+    """E = sum over all (k, k') blocks of the block energy with targets at k,
+    occupied orbitals at k' and q = k - k' (not folded back into the zone).
+
+    ``weights[k]`` already carry the 1/N_k of the mesh average.  The point
+    q + G = 0 (k = k', G = 0) takes ``k0``.
+    """
+    e = 0.0
+    for kt in range(len(sets)):
+        for ko in range(len(sets)):
+            q = np.asarray(kpts[kt], dtype=np.float64) - np.asarray(kpts[ko], dtype=np.float64)
+            e += fock_energy(a, n, miller, q, sets[ko], weights[ko], sets[kt], weights[kt], ecut_fock, k0, method)
+    return e
+
+
+def fock_energy_kmesh_grad(a, n, miller, kpts, sets, weights, ecut_fock: float = 0.0, k0: float = 0.0,
+                           method: str = "auto"):
+    """Wirtinger derivatives dE/dconj(c_k) of ``fock_energy_kmesh``: the sum of
+    each block's target and occupied gradients."""
+    grads = [np.zeros_like(np.asarray(c, dtype=np.complex128)) for c in sets]
+    for kt in range(len(sets)):
+        for ko in range(len(sets)):
+            q = np.asarray(kpts[kt], dtype=np.float64) - np.asarray(kpts[ko], dtype=np.float64)
+            go, gt = fock_energy_grad(a, n, miller, q, sets[ko], weights[ko], sets[kt], weights[kt],
+                                      ecut_fock, k0, method)
+            grads[ko] += go
+            grads[kt] += gt
+    return grads

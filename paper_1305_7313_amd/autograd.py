@@ -38,3 +38,30 @@ class ExchangeEnergy(torch.autograd.Function):
 
 def exchange_energy(c_occ, c_tgt, f_occ, g_tgt, cell, q=(0.0, 0.0, 0.0)):
     return ExchangeEnergy.apply(c_occ, c_tgt, f_occ, g_tgt, cell, q)
+
+
+class ExchangeEnergyKMesh(torch.autograd.Function):
+    """E_x over a k-point mesh for C [nk, nb, npw]; W [nk, nb] are occupation / N_k."""
+
+    @staticmethod
+    def forward(ctx, C, W, cell, kpts):
+        ws = fock.workspace_kmesh(cell, fock.dtype_code(C), C.shape[0], C.shape[1], C.device)
+        ex = fock.fock_energy_kmesh(cell, kpts, C, W, ws=ws)
+        ctx.save_for_backward(C, W)
+        ctx.cell, ctx.kpts = cell, kpts
+        return ex
+
+    @staticmethod
+    def backward(ctx, grad):
+        C, W = ctx.saved_tensors
+        if not ctx.needs_input_grad[0]:
+            return None, None, None, None
+        scale = grad.detach().to(device=C.device, dtype=torch.float64).mul(2.0).contiguous()
+        G = torch.empty_like(C)
+        ws = fock.workspace_kmesh(ctx.cell, fock.dtype_code(C), C.shape[0], C.shape[1], C.device)
+        fock.fock_energy_kmesh_backward(ctx.cell, ctx.kpts, C, W, scale, [G[k] for k in range(C.shape[0])], ws=ws)
+        return G, None, None, None
+
+
+def exchange_energy_kmesh(C, W, cell, kpts):
+    return ExchangeEnergyKMesh.apply(C, W, cell, kpts)

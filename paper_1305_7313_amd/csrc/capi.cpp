@@ -76,6 +76,7 @@ struct TraceScope {
   }
 };
 #define FX_TRACE(kc) TraceScope trace_scope_##__LINE__(kc, s)
+#define FX_TRACE_S(kc) TraceScope trace_scope_s(kc, s)
 
 // ---------------------------------------------------------------------------
 // Plans: per device, grid, lattice, dtype and sphere.
@@ -310,6 +311,27 @@ Layout layout(long long N, int cplx_bytes, int ngroups, int n_occ, int n_tgt) {
   return L;
 }
 
+// k-mesh jobs: every set's real-space orbitals stay resident; one
+// accumulator block; tile partials for every (k <= k') block.
+Layout layout_kmesh(long long N, int cplx_bytes, int ngroups, int nk, int nbmax) {
+  const Tiles t = tiles_for(nbmax, nbmax);
+  const size_t nb = (size_t)N * cplx_bytes;
+  const int ntb = (nbmax + t.ti - 1) / t.ti;
+  const int ntiles = (nk * (nk + 1) / 2) * (ntb > 0 ? ntb * ntb : 1);
+  Layout L;
+  size_t off = 0;
+  L.phiA = off; off += align_up(nb * (size_t)nbmax * nk);
+  L.phiB = off; off += align_up(nb * (size_t)nbmax);
+  L.acc = off; off += align_up(nb * (size_t)t.tj);
+  L.w = off; off += align_up(nb * (size_t)t.ti * t.tj);
+  L.epart = off; off += align_up(sizeof(double) * (size_t)t.ti * t.tj * ngroups);
+  L.tile_e = off; off += align_up(sizeof(double) * (size_t)ntiles);
+  L.k0 = off; off += align_up(sizeof(double));
+  L.gbpart = off; off += align_up(sizeof(double) * kGbParts);
+  L.total = off;
+  return L;
+}
+
 fock_status check_orbs(const fock_orbs* o, int npw, const char* name) {
   if (!o) return fail(FOCK_E_ARG, std::string(name) + " is NULL");
   if (o->nb < 0) return fail(FOCK_E_ARG, std::string(name) + ".nb < 0");
@@ -464,67 +486,87 @@ struct Engine {
     return sizeof(T) == 8 ? 0 : 1;
   }
 
-  // The band-pair loop.  energy == false: apply -> out; true: energy partials -> tile_e.
-  // sym: one orbital block at q = 0; only tiles I <= J are transformed, and
-  // v_ji = conj(v_ij) supplies the mirrored pairs.
-  fock_status pairs(const fock_cell* cell, const double q[3], bool q_zero, const void* phiA, const double* fA,
-                    int nA, const void* phiB, const double* gB, int nB, char* ws, const Layout& L, bool energy,
-                    bool sym, void* out, int ldo, double s0, const double* wout, const double* gscale) {
-    const Tiles t = tiles_for(nA, nB);
+  // One band-pair job: occupied block A (real space, weights fA) against
+  // target block B.  energy: per-tile FP64 partials into tile_e[tile_base..];
+  // apply with acc_full == null: per-target-tile accumulators, each finished
+  // into out; apply with acc_full: accumulate into acc_full[nB][N] (zeroed by
+  // the caller, finished by the caller).  sym: A == B at q = 0, tiles I <= J
+  // only, v_ji = conj(v_ij) supplies the mirrored pairs (needs acc_full).
+  struct PairJob {
+    const void* phiA = nullptr;
+    const double* fA = nullptr;
+    int nA = 0;
+    const void* phiB = nullptr;
+    const double* gB = nullptr;
+    int nB = 0;
+    bool sym = false, energy = false;
+    double escale = 1.0;
+    int tile_base = 0;
+    void* acc_full = nullptr;
+    void* out = nullptr;
+    int ldo = 0;
+    double s0 = 0.0;
+    const double* wout = nullptr;
+    const double* gscale = nullptr;
+  };
+
+  fock_status pairs(const KernelParams& kp, char* ws, const Layout& L, const PairJob& J, int* ntiles) {
+    const Tiles t = tiles_for(J.nA, J.nB);
     void* w = ws + L.w;
     double* epart = reinterpret_cast<double*>(ws + L.epart);
-    double* tile_e = reinterpret_cast<double*>(ws + L.tile_e);
-    double* d_k0 = reinterpret_cast<double*>(ws + L.k0);
-    KernelParams kp = kparams(q, q_zero, cell, d_k0);
+    double* tile_e = reinterpret_cast<double*>(ws + L.tile_e) + J.tile_base;
+    const size_t box = (size_t)P.N * sizeof(cx<T>);
     fock_status st;
     int tile = 0;
-    if (!sym) {
-      void* acc = ws + L.acc;
-      for (int j0 = 0; j0 < nB; j0 += t.tj) {
-        const int tj = (nB - j0) < t.tj ? (nB - j0) : t.tj;
-        if (!energy) {
+    if (!J.sym) {
+      for (int j0 = 0; j0 < J.nB; j0 += t.tj) {
+        const int tj = (J.nB - j0) < t.tj ? (J.nB - j0) : t.tj;
+        void* acc = J.acc_full ? static_cast<void*>(static_cast<char*>(J.acc_full) + (size_t)j0 * box)
+                               : static_cast<void*>(ws + L.acc);
+        if (!J.energy && !J.acc_full) {
           FX_TRACE(KC_ZERO);
           FX_HIP(launch_zero<T>(acc, P.N * tj, s));
         }
-        for (int i0 = 0; i0 < nA; i0 += t.ti, ++tile) {
-          const int ti = (nA - i0) < t.ti ? (nA - i0) : t.ti;
-          PlaneArgs la = plane_args(phiA, phiB, w, acc, fA, i0, j0, ti, tj);
-          if ((st = tile_forward(la, kp, energy, epart)) != FOCK_OK) return st;
-          if (energy) {
+        for (int i0 = 0; i0 < J.nA; i0 += t.ti, ++tile) {
+          const int ti = (J.nA - i0) < t.ti ? (J.nA - i0) : t.ti;
+          PlaneArgs la = plane_args(J.phiA, J.phiB, w, acc, J.fA, i0, j0, ti, tj);
+          if ((st = tile_forward(la, kp, J.energy, epart)) != FOCK_OK) return st;
+          if (J.energy) {
             FX_TRACE(KC_REDUCE);
-            FX_HIP(launch_energy_tile(epart, ngroups, fA, gB, i0, j0, ti, tj, 0, tile_e + tile, s));
+            FX_HIP(launch_energy_tile(epart, ngroups, J.fA, J.gB, i0, j0, ti, tj, 0, J.escale, tile_e + tile, s));
           } else {
             FX_TRACE(KC_P3);
             FX_HIP(launch_plane<T>(PLANE_INV_MAC, P.n[1], P.n[2], la, tj * P.n[0], s));
           }
         }
-        if (!energy && (st = finish(acc, tj, j0, out, ldo, s0, wout, gscale)) != FOCK_OK) return st;
+        if (!J.energy && !J.acc_full &&
+            (st = finish(acc, tj, j0, J.out, J.ldo, J.s0, J.wout, J.gscale)) != FOCK_OK)
+          return st;
       }
+      if (ntiles) *ntiles = tile;
       return FOCK_OK;
     }
-    // symmetric schedule: accumulators for every orbital live in the (unused) phiB region
+    // symmetric schedule
+    if (!J.energy && !J.acc_full) return fail(FOCK_E_ARG, "internal: symmetric apply needs full accumulators");
     const int T0 = t.ti < kMacTile ? t.ti : kMacTile;
-    void* acc_all = ws + L.phiB;
-    if (!energy) {
-      FX_TRACE(KC_ZERO);
-      FX_HIP(launch_zero<T>(acc_all, P.N * nB, s));
-    }
-    for (int j0 = 0; j0 < nB; j0 += T0) {
-      const int tj = (nB - j0) < T0 ? (nB - j0) : T0;
+    void* acc_all = J.acc_full;
+    const void* phiA = J.phiA;
+    for (int j0 = 0; j0 < J.nB; j0 += T0) {
+      const int tj = (J.nB - j0) < T0 ? (J.nB - j0) : T0;
       for (int i0 = 0; i0 <= j0; i0 += T0, ++tile) {
-        const int ti = (nA - i0) < T0 ? (nA - i0) : T0;
-        PlaneArgs la = plane_args(phiA, phiA, w, nullptr, fA, i0, j0, ti, tj);
-        if ((st = tile_forward(la, kp, energy, epart)) != FOCK_OK) return st;
-        if (energy) {
+        const int ti = (J.nA - i0) < T0 ? (J.nA - i0) : T0;
+        PlaneArgs la = plane_args(phiA, phiA, w, nullptr, J.fA, i0, j0, ti, tj);
+        if ((st = tile_forward(la, kp, J.energy, epart)) != FOCK_OK) return st;
+        if (J.energy) {
           FX_TRACE(KC_REDUCE);
-          FX_HIP(launch_energy_tile(epart, ngroups, fA, gB, i0, j0, ti, tj, 1, tile_e + tile, s));
+          FX_HIP(launch_energy_tile(epart, ngroups, J.fA, J.gB, i0, j0, ti, tj, 1, J.escale, tile_e + tile, s));
           continue;
         }
         if (sym_schedule() == 0) {
           // fused inverse plane FFT + multiply-accumulate into acc_J; off-diagonal
           // tiles leave v_ij in real space for the mirrored half.
           PlaneArgs lp = la;
-          lp.acc = static_cast<char*>(acc_all) + (size_t)j0 * P.N * sizeof(cx<T>);
+          lp.acc = static_cast<char*>(acc_all) + (size_t)j0 * box;
           lp.store_v = i0 != j0;
           {
             FX_TRACE(KC_P3);
@@ -532,7 +574,7 @@ struct Engine {
           }
           if (i0 != j0) {
             PlaneArgs lb = lp;
-            lb.acc = static_cast<char*>(acc_all) + (size_t)i0 * P.N * sizeof(cx<T>);
+            lb.acc = static_cast<char*>(acc_all) + (size_t)i0 * box;
             FX_TRACE(KC_P3B);
             FX_HIP(launch_mac_conj<T>(lb, P.n[1] * P.n[2], ti * P.n[0], s));
           }
@@ -549,7 +591,7 @@ struct Engine {
         MacArgs ma{};
         ma.w = w;
         ma.phi = phiA;
-        ma.f = fA;
+        ma.f = J.fA;
         ma.acc = acc_all;
         ma.N = P.N;
         ma.i0 = i0;
@@ -561,10 +603,17 @@ struct Engine {
         FX_HIP(launch_mac_pair<T>(ma, s));
       }
     }
-    if (!energy && (st = finish(acc_all, nB, 0, out, ldo, s0, wout, gscale)) != FOCK_OK) return st;
+    if (ntiles) *ntiles = tile;
     return FOCK_OK;
   }
 };
+
+// number of energy tiles a job produces
+int energy_tiles(int nA, int nB, bool sym) {
+  const Tiles t = tiles_for(nA, nB);
+  const int nti = (nA + t.ti - 1) / t.ti, ntj = (nB + t.tj - 1) / t.tj;
+  return sym ? nti * (nti + 1) / 2 : nti * ntj;
+}
 
 template <typename T>
 fock_status apply_impl(const fock_cell* cell, const Plan& P, const double q[3], bool q_zero, const fock_orbs* occ,
@@ -572,8 +621,8 @@ fock_status apply_impl(const fock_cell* cell, const Plan& P, const double q[3], 
                        const double* wout, const double* gscale) {
   Engine<T> E(P, s);
   if (tgt->nb == 0) return FOCK_OK;
-  const double* d_k0 = reinterpret_cast<double*>(ws + L.k0);
-  fock_status st = E.g0_constant(cell, q_zero, const_cast<double*>(d_k0), reinterpret_cast<double*>(ws + L.gbpart));
+  double* d_k0 = reinterpret_cast<double*>(ws + L.k0);
+  fock_status st = E.g0_constant(cell, q_zero, d_k0, reinterpret_cast<double*>(ws + L.gbpart));
   if (st != FOCK_OK) return st;
   void* phiA = ws + L.phiA;
   void* phiB = ws + L.phiB;
@@ -581,20 +630,30 @@ fock_status apply_impl(const fock_cell* cell, const Plan& P, const double q[3], 
   if ((st = E.to_real_space(occ->c, occ->ld, occ->nb, phiA)) != FOCK_OK) return st;
   if (same) phiB = phiA;
   else if ((st = E.to_real_space(tgt->c, tgt->ld, tgt->nb, phiB)) != FOCK_OK) return st;
-  if (occ->nb == 0) {
-    // no occupied states: V_x psi = 0 on the sphere
-    void* acc = ws + L.acc;
-    const Tiles t = tiles_for(1, tgt->nb);
-    FX_HIP(launch_zero<T>(acc, P.N * t.tj, s));
-    for (int j0 = 0; j0 < tgt->nb; j0 += t.tj) {
-      const int tj = (tgt->nb - j0) < t.tj ? (tgt->nb - j0) : t.tj;
-      char* o = static_cast<char*>(out) + (size_t)j0 * tgt->ld * sizeof(cx<T>);
-      FX_HIP(launch_gather<T>(acc, P.N, P.d_slot, P.npw, tj, o, tgt->ld, 0.0, nullptr, 0, nullptr, s));
+  typename Engine<T>::PairJob J;
+  J.phiA = phiA;
+  J.fA = occ->w;
+  J.nA = occ->nb;
+  J.phiB = phiB;
+  J.gB = tgt->w;
+  J.nB = tgt->nb;
+  J.sym = same && q_zero && occ->nb > 0;
+  J.out = out;
+  J.ldo = tgt->ld;
+  J.s0 = s0;
+  J.wout = wout;
+  J.gscale = gscale;
+  if (J.sym || occ->nb == 0) {
+    // every target accumulates in the (then unused) phiB region; finished once
+    J.acc_full = ws + L.phiB;
+    {
+      FX_TRACE_S(KC_ZERO);
+      FX_HIP(launch_zero<T>(J.acc_full, P.N * tgt->nb, s));
     }
-    return FOCK_OK;
+    if (occ->nb > 0 && (st = E.pairs(E.kparams(q, q_zero, cell, d_k0), ws, L, J, nullptr)) != FOCK_OK) return st;
+    return E.finish(J.acc_full, tgt->nb, 0, out, tgt->ld, occ->nb > 0 ? s0 : 0.0, wout, gscale);
   }
-  return E.pairs(cell, q, q_zero, phiA, occ->w, occ->nb, phiB, tgt->w, tgt->nb, ws, L, false, same && q_zero, out,
-                 tgt->ld, s0, wout, gscale);
+  return E.pairs(E.kparams(q, q_zero, cell, d_k0), ws, L, J, nullptr);
 }
 
 template <typename T>
@@ -614,13 +673,17 @@ fock_status energy_impl(const fock_cell* cell, const Plan& P, const double q[3],
   if ((st = E.to_real_space(occ->c, occ->ld, occ->nb, phiA)) != FOCK_OK) return st;
   if (same) phiB = phiA;
   else if ((st = E.to_real_space(tgt->c, tgt->ld, tgt->nb, phiB)) != FOCK_OK) return st;
-  const bool sym = same && q_zero;
-  st = E.pairs(cell, q, q_zero, phiA, occ->w, occ->nb, phiB, tgt->w, tgt->nb, ws, L, true, sym, nullptr, 0, 0.0,
-               nullptr, nullptr);
-  if (st != FOCK_OK) return st;
-  const Tiles t = tiles_for(occ->nb, tgt->nb);
-  const int nti = (occ->nb + t.ti - 1) / t.ti, ntj = (tgt->nb + t.tj - 1) / t.tj;
-  const int ntiles = sym ? nti * (nti + 1) / 2 : nti * ntj;
+  typename Engine<T>::PairJob J;
+  J.phiA = phiA;
+  J.fA = occ->w;
+  J.nA = occ->nb;
+  J.phiB = phiB;
+  J.gB = tgt->w;
+  J.nB = tgt->nb;
+  J.sym = same && q_zero;
+  J.energy = true;
+  int ntiles = 0;
+  if ((st = E.pairs(E.kparams(q, q_zero, cell, d_k0), ws, L, J, &ntiles)) != FOCK_OK) return st;
   const double scale = -0.5 / (P.omega * (double)P.N * (double)P.N);
   FX_HIP(launch_energy_final(reinterpret_cast<double*>(ws + L.tile_e), ntiles, scale, ex, s));
   return FOCK_OK;
@@ -680,6 +743,116 @@ fock_status prepare(const fock_cell* cell, const double q[3], int dtype, const f
     return fail(FOCK_E_WORKSPACE, buf);
   }
   return get_plan(cell, dtype, &out->plan);
+}
+
+// Exchange energy over a k-point mesh and its gradient.  Block (k, k')
+// pairs targets at k with occupied orbitals at k', q = k - k'.
+template <typename T>
+fock_status kmesh_impl(const fock_cell* cell, const Plan& P, int nk, const double* kpts, const fock_orbs* sets,
+                       char* ws, const Layout& L, hipStream_t s, double* ex, const double* grad_ex,
+                       void* const* grad) {
+  Engine<T> E(P, s);
+  const size_t box = (size_t)P.N * sizeof(cx<T>);
+  int nbmax = 0;
+  for (int k = 0; k < nk; ++k) nbmax = sets[k].nb > nbmax ? sets[k].nb : nbmax;
+  double* d_k0 = reinterpret_cast<double*>(ws + L.k0);
+  fock_status st = E.g0_constant(cell, true, d_k0, reinterpret_cast<double*>(ws + L.gbpart));
+  if (st != FOCK_OK) return st;
+  auto phi = [&](int k) { return static_cast<void*>(ws + L.phiA + (size_t)k * nbmax * box); };
+  for (int k = 0; k < nk; ++k)
+    if ((st = E.to_real_space(sets[k].c, sets[k].ld, sets[k].nb, phi(k))) != FOCK_OK) return st;
+  auto qof = [&](int kt, int ko, double q[3]) {
+    for (int a = 0; a < 3; ++a) q[a] = kpts[3 * kt + a] - kpts[3 * ko + a];
+    return q[0] == 0.0 && q[1] == 0.0 && q[2] == 0.0;
+  };
+  if (ex) {
+    // E_kk' = E_k'k: blocks k <= k' only, off-diagonal ones counted twice
+    int base = 0;
+    for (int k = 0; k < nk; ++k) {
+      for (int kp = k; kp < nk; ++kp) {
+        if (sets[k].nb == 0 || sets[kp].nb == 0) continue;
+        double q[3];
+        const bool qz = qof(k, kp, q);
+        typename Engine<T>::PairJob J;
+        J.phiA = phi(kp);
+        J.fA = sets[kp].w;
+        J.nA = sets[kp].nb;
+        J.phiB = phi(k);
+        J.gB = sets[k].w;
+        J.nB = sets[k].nb;
+        J.sym = kp == k;
+        J.energy = true;
+        J.escale = kp == k ? 1.0 : 2.0;
+        J.tile_base = base;
+        int nt = 0;
+        if ((st = E.pairs(E.kparams(q, qz, cell, d_k0), ws, L, J, &nt)) != FOCK_OK) return st;
+        base += nt;
+      }
+    }
+    const double scale = -0.5 / (P.omega * (double)P.N * (double)P.N);
+    FX_HIP(launch_energy_final(reinterpret_cast<double*>(ws + L.tile_e), base, scale, ex, s));
+  }
+  if (grad) {
+    // dE/d conj(c_jk) = w_jk sum_k' (V_x with occupied set k', q = k - k') psi_jk
+    void* acc = ws + L.phiB;
+    const double s0 = -1.0 / (P.omega * (double)P.N * (double)P.N);
+    for (int k = 0; k < nk; ++k) {
+      if (sets[k].nb == 0 || !grad[k]) continue;
+      {
+        FX_TRACE_S(KC_ZERO);
+        FX_HIP(launch_zero<T>(acc, P.N * sets[k].nb, s));
+      }
+      for (int kp = 0; kp < nk; ++kp) {
+        if (sets[kp].nb == 0) continue;
+        double q[3];
+        const bool qz = qof(k, kp, q);
+        typename Engine<T>::PairJob J;
+        J.phiA = phi(kp);
+        J.fA = sets[kp].w;
+        J.nA = sets[kp].nb;
+        J.phiB = phi(k);
+        J.gB = sets[k].w;
+        J.nB = sets[k].nb;
+        J.sym = kp == k;
+        J.acc_full = acc;
+        if ((st = E.pairs(E.kparams(q, qz, cell, d_k0), ws, L, J, nullptr)) != FOCK_OK) return st;
+      }
+      if ((st = E.finish(acc, sets[k].nb, 0, grad[k], sets[k].ld, s0, sets[k].w, grad_ex)) != FOCK_OK) return st;
+    }
+  }
+  return FOCK_OK;
+}
+
+fock_status kmesh_prepare(const fock_cell* cell, int32_t nk, const double* kpts, int32_t dtype, const fock_orbs* sets,
+                          void* ws, size_t ws_bytes, std::shared_ptr<Plan>* plan, Layout* L) {
+  fock_status st = check_cell_host(cell, dtype);
+  if (st != FOCK_OK) return st;
+  if (!grid_supported(cell->n, dtype))
+    return fail(FOCK_E_UNSUPPORTED_GRID, "no compiled transforms for grid " + grid_str(cell->n));
+  if (nk <= 0 || !kpts || !sets) return fail(FOCK_E_ARG, "need nk > 0, kpts and sets");
+  int nbmax = 0;
+  for (int k = 0; k < nk; ++k) {
+    if ((st = check_orbs(&sets[k], cell->npw, "sets[k]")) != FOCK_OK) return st;
+    nbmax = sets[k].nb > nbmax ? sets[k].nb : nbmax;
+    for (int a = 0; a < 3; ++a)
+      if (!std::isfinite(kpts[3 * k + a])) return fail(FOCK_E_ARG, "k-points must be finite");
+  }
+  for (int k = 0; k < nk; ++k)
+    for (int kp = 0; kp < nk; ++kp) {
+      const double q[3] = {kpts[3 * k] - kpts[3 * kp], kpts[3 * k + 1] - kpts[3 * kp + 1],
+                           kpts[3 * k + 2] - kpts[3 * kp + 2]};
+      bool qz;
+      if ((st = check_q(cell, q, &qz)) != FOCK_OK) return st;
+    }
+  const long long N = (long long)cell->n[0] * cell->n[1] * cell->n[2];
+  const int ngroups = cell->n[1] * cell->n[2] / pencil_columns(cell->n[0], tbytes_of(dtype));
+  *L = layout_kmesh(N, dtype == FOCK_C128 ? 16 : 8, ngroups, nk, nbmax);
+  if (!ws || ws_bytes < L->total) {
+    char buf[160];
+    std::snprintf(buf, sizeof buf, "workspace of %zu bytes is smaller than the %zu needed", ws_bytes, L->total);
+    return fail(FOCK_E_WORKSPACE, buf);
+  }
+  return get_plan(cell, dtype, plan);
 }
 
 }  // namespace
@@ -746,6 +919,41 @@ fock_status fock_energy_backward(const fock_cell* cell, const double q[3], int32
     if (st != FOCK_OK) return st;
   }
   return FOCK_OK;
+}
+
+size_t fock_workspace_size_kmesh(const fock_cell* cell, int32_t dtype, int32_t nk, int32_t nb_max) {
+  if (!cell || nk <= 0 || nb_max < 0 || (dtype != FOCK_C128 && dtype != FOCK_C64)) return 0;
+  if (!grid_supported(cell->n, dtype)) return 0;
+  const long long N = (long long)cell->n[0] * cell->n[1] * cell->n[2];
+  const int ngroups = cell->n[1] * cell->n[2] / pencil_columns(cell->n[0], tbytes_of(dtype));
+  return layout_kmesh(N, dtype == FOCK_C128 ? 16 : 8, ngroups, nk, nb_max).total;
+}
+
+fock_status fock_energy_kmesh(const fock_cell* cell, int32_t nk, const double* kpts, int32_t dtype,
+                              const fock_orbs* sets, double* ex_out, void* ws, size_t ws_bytes, void* stream) {
+  std::shared_ptr<Plan> plan;
+  Layout L;
+  fock_status st = kmesh_prepare(cell, nk, kpts, dtype, sets, ws, ws_bytes, &plan, &L);
+  if (st != FOCK_OK) return st;
+  if (!ex_out) return fail(FOCK_E_ARG, "ex_out is NULL");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  char* w = static_cast<char*>(ws);
+  if (dtype == FOCK_C128) return kmesh_impl<double>(cell, *plan, nk, kpts, sets, w, L, s, ex_out, nullptr, nullptr);
+  return kmesh_impl<float>(cell, *plan, nk, kpts, sets, w, L, s, ex_out, nullptr, nullptr);
+}
+
+fock_status fock_energy_kmesh_backward(const fock_cell* cell, int32_t nk, const double* kpts, int32_t dtype,
+                                       const fock_orbs* sets, const double* grad_ex, void* const* grad, void* ws,
+                                       size_t ws_bytes, void* stream) {
+  std::shared_ptr<Plan> plan;
+  Layout L;
+  fock_status st = kmesh_prepare(cell, nk, kpts, dtype, sets, ws, ws_bytes, &plan, &L);
+  if (st != FOCK_OK) return st;
+  if (!grad_ex || !grad) return fail(FOCK_E_ARG, "grad_ex and grad must not be NULL");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  char* w = static_cast<char*>(ws);
+  if (dtype == FOCK_C128) return kmesh_impl<double>(cell, *plan, nk, kpts, sets, w, L, s, nullptr, grad_ex, grad);
+  return kmesh_impl<float>(cell, *plan, nk, kpts, sets, w, L, s, nullptr, grad_ex, grad);
 }
 
 fock_status fock_fft3d(const int32_t n[3], int32_t dtype, int32_t sign, void* x, int32_t nb, void* stream) {

@@ -23,7 +23,7 @@ hipError_t launch_gather(const void* box, long long N, const int* slot, int npw,
                          const double* w, int j0, const double* g, hipStream_t s);
 
 hipError_t launch_energy_tile(const double* epart, int ngroups, const double* f, const double* g, int i0, int j0, int ti,
-                              int tj, int sym, double* tile_e, hipStream_t s);
+                              int tj, int sym, double escale, double* tile_e, hipStream_t s);
 hipError_t launch_energy_final(const double* tile_e, int ntiles, double scale, double* ex, hipStream_t s);
 hipError_t launch_gb(const KernelParams& kp, const int n[3], const int nq[3], double alpha, double head,
                      double* partial, int nparts, double* k0, hipStream_t s);

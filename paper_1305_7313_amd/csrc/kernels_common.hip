@@ -9,7 +9,7 @@ namespace fockx {
 // diagonal tile (i0 == j0) only ii < jj counts twice, ii == jj once.
 __global__ void energy_tile_kernel(const double* __restrict__ epart, int ngroups, const double* __restrict__ f,
                                    const double* __restrict__ g, int i0, int j0, int ti, int tj, int sym,
-                                   double* __restrict__ tile_e) {
+                                   double escale, double* __restrict__ tile_e) {
   __shared__ double red[16];
   double acc = 0.0;
   for (int pr = threadIdx.x; pr < ti * tj; pr += blockDim.x) {
@@ -27,7 +27,7 @@ __global__ void energy_tile_kernel(const double* __restrict__ epart, int ngroups
     acc += wgt * s;
   }
   const double tot = block_sum(acc, red);
-  if (threadIdx.x == 0) *tile_e = tot;
+  if (threadIdx.x == 0) *tile_e = escale * tot;
 }
 
 // ex = scale * sum_t tile_e[t]   (one thread, fixed order)
@@ -92,9 +92,9 @@ int pencil_columns(int n1, int tbytes) {
 }
 
 hipError_t launch_energy_tile(const double* epart, int ngroups, const double* f, const double* g, int i0, int j0,
-                              int ti, int tj, int sym, double* tile_e, hipStream_t s) {
+                              int ti, int tj, int sym, double escale, double* tile_e, hipStream_t s) {
   hipLaunchKernelGGL(energy_tile_kernel, dim3(1), dim3(256), 0, s, epart, ngroups, f, g, i0, j0, ti, tj, sym,
-                     tile_e);
+                     escale, tile_e);
   return hipGetLastError();
 }
 

@@ -75,6 +75,16 @@ def lib():
         L.fock_energy_backward.restype = ctypes.c_int
         L.fock_energy_backward.argtypes = common + [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                                     ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
+        L.fock_workspace_size_kmesh.restype = ctypes.c_size_t
+        L.fock_workspace_size_kmesh.argtypes = [P(fock_cell), ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
+        L.fock_energy_kmesh.restype = ctypes.c_int
+        L.fock_energy_kmesh.argtypes = [P(fock_cell), ctypes.c_int32, P(ctypes.c_double), ctypes.c_int32,
+                                        P(fock_orbs), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                        ctypes.c_void_p]
+        L.fock_energy_kmesh_backward.restype = ctypes.c_int
+        L.fock_energy_kmesh_backward.argtypes = [P(fock_cell), ctypes.c_int32, P(ctypes.c_double), ctypes.c_int32,
+                                                 P(fock_orbs), ctypes.c_void_p, P(ctypes.c_void_p),
+                                                 ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
         L.fock_fft3d.restype = ctypes.c_int
         L.fock_fft3d.argtypes = [P(ctypes.c_int32), ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
                                  ctypes.c_int32, ctypes.c_void_p]
@@ -250,3 +260,56 @@ def fock_trace_read(reset: bool = True) -> dict:
     cnt = (ctypes.c_longlong * n)()
     lib().fock_trace_read(ms, cnt, 1 if reset else 0)
     return {lib().fock_trace_name(k).decode(): (float(ms[k]), int(cnt[k])) for k in range(n)}
+
+
+# ---------------------------------------------------------------------------
+# k-point mesh
+# ---------------------------------------------------------------------------
+def _kmesh_args(kpts, C, W):
+    nk = int(C.shape[0])
+    kp = np.ascontiguousarray(np.asarray(kpts, dtype=np.float64).reshape(nk, 3))
+    sets = (fock_orbs * nk)()
+    for k in range(nk):
+        sets[k] = orbs(C[k], W[k])
+    return nk, kp, sets
+
+
+def fock_workspace_size_kmesh(cell: Cell, dtype: int, nk: int, nb_max: int) -> int:
+    return int(lib().fock_workspace_size_kmesh(ctypes.byref(cell.c), int(dtype), int(nk), int(nb_max)))
+
+
+def workspace_kmesh(cell: Cell, dtype: int, nk: int, nb_max: int, device):
+    import torch
+    nbytes = fock_workspace_size_kmesh(cell, dtype, nk, nb_max)
+    if nbytes == 0:
+        raise FockError(FOCK_E_UNSUPPORTED_GRID, "fock_workspace_size_kmesh returned 0 for this cell")
+    return torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+
+def fock_energy_kmesh(cell: Cell, kpts, C, W, out=None, ws=None):
+    """Exchange energy over a k-mesh: C [nk, nb, npw] device coefficients, W [nk, nb] float64
+    weights (occupation / N_k).  Returns a device float64 scalar (C call: fock_energy_kmesh)."""
+    import torch
+    dt = dtype_code(C)
+    nk, kp, sets = _kmesh_args(kpts, C, W)
+    if out is None:
+        out = torch.empty((), dtype=torch.float64, device=C.device)
+    if ws is None:
+        ws = workspace_kmesh(cell, dt, nk, int(C.shape[1]), C.device)
+    _check(lib().fock_energy_kmesh(ctypes.byref(cell.c), nk, kp.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                   dt, sets, out.data_ptr(), ws.data_ptr(), ws.numel(), _stream(C.device)))
+    return out
+
+
+def fock_energy_kmesh_backward(cell: Cell, kpts, C, W, grad_ex, grad, ws=None):
+    """grad[k] = grad_ex * dE/dconj(C[k]) (C call: fock_energy_kmesh_backward)."""
+    dt = dtype_code(C)
+    nk, kp, sets = _kmesh_args(kpts, C, W)
+    ptrs = (ctypes.c_void_p * nk)(*[grad[k].data_ptr() for k in range(nk)])
+    if ws is None:
+        ws = workspace_kmesh(cell, dt, nk, int(C.shape[1]), C.device)
+    _check(lib().fock_energy_kmesh_backward(ctypes.byref(cell.c), nk,
+                                            kp.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), dt, sets,
+                                            grad_ex.data_ptr(), ptrs, ws.data_ptr(), ws.numel(),
+                                            _stream(C.device)))
+    return grad

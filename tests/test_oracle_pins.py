@@ -260,3 +260,55 @@ def test_mutations_are_caught(skew, monkeypatch):
     s, occ, tgt, f = skew
     v = exx.fock_apply(A_SKEW, N_SKEW, s.miller, Q_SKEW, occ, f, tgt)
     assert rel(v, definitions.fock_apply_direct(A_SKEW, s.miller, Q_SKEW, occ, f, tgt)) > 1e-6
+
+
+def gaussian_bloch_sets(L, n, sigma, nq):
+    """Bloch sums of one Gaussian per cell: c_k(G) ~ exp(-sigma^2 |k+G|^2).
+
+    The pair density of the sets at k' and k then has the coefficient
+    Omega^-1 exp(-sigma^2 |q+G|^2 / 2) at G, q = k - k' (a normalised Gaussian
+    charge of width sigma, carried by the Bloch phase q)."""
+    a = synth.cubic_cell(L)
+    mill = synth.sphere_miller(a, n, synth.alias_free_ecut(a, n))
+    kpts = synth.kmesh_points(a, nq)
+    g = mill.astype(np.float64) @ synth.reciprocal_rows(a)
+    sets = []
+    for k in kpts:
+        kg = g + k[None, :]
+        c = np.exp(-sigma ** 2 * np.einsum("ij,ij->i", kg, kg))
+        sets.append((c / np.linalg.norm(c))[None, :].astype(np.complex128))
+    return a, mill, kpts, sets
+
+
+# P7 on a k-mesh: a Gaussian Wannier function, weights 1/N_k.  The mesh sum
+# with the mesh's Gygi-Baldereschi constant (width sigma^2) is exact for the
+# Gaussian charge, so E is again the isolated self-exchange -1/(2 sigma sqrt pi).
+def test_p7_gaussian_kmesh_gb():
+    L, n, sigma, nq = 20.0, (64, 64, 64), 1.2, (2, 2, 2)
+    a, mill, kpts, sets = gaussian_bloch_sets(L, n, sigma, nq)
+    nk = len(kpts)
+    k0 = exx.gb_constant(a, n, nq, sigma ** 2)
+    e = exx.fock_energy_kmesh(a, n, mill, kpts, sets, [np.array([1.0 / nk])] * nk, k0=k0)
+    assert abs(e + 1.0 / (2 * sigma * np.sqrt(np.pi))) < 1e-12 * abs(e)
+
+
+def test_kmesh_gradient_finite_difference():
+    a = synth.cubic_cell(8.0)
+    n = (12, 12, 12)
+    s = synth.make_system(a, n)
+    nq = (2, 1, 1)
+    kpts = synth.kmesh_points(a, nq)
+    sets = [synth.random_orbitals(a, s.miller, 2, 20 + k) for k in range(len(kpts))]
+    wts = [np.array([0.5, 0.4]), np.array([0.45, 0.3])]
+    k0 = exx.gb_constant(a, n, nq, 0.5)
+    grads = exx.fock_energy_kmesh_grad(a, n, s.miller, kpts, sets, wts, k0=k0)
+    rng = np.random.default_rng(8)
+    d = [rng.standard_normal(c.shape) + 1j * rng.standard_normal(c.shape) for c in sets]
+    nrm = np.sqrt(sum(np.sum(np.abs(x) ** 2) for x in d))
+    d = [x / nrm for x in d]
+    h = 1e-4
+    ep = exx.fock_energy_kmesh(a, n, s.miller, kpts, [c + h * x for c, x in zip(sets, d)], wts, k0=k0)
+    em = exx.fock_energy_kmesh(a, n, s.miller, kpts, [c - h * x for c, x in zip(sets, d)], wts, k0=k0)
+    fd = (ep - em) / (2 * h)
+    an = 2.0 * sum(np.sum(np.conj(g) * x).real for g, x in zip(grads, d))
+    assert abs(fd - an) < 1e-8 * abs(an)
