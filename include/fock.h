@@ -129,6 +129,32 @@ fock_status fock_energy_kmesh_backward(const fock_cell *cell, int32_t nk, const 
                                        const fock_orbs *sets, const double *grad_ex, void *const *grad, void *ws,
                                        size_t ws_bytes, void *stream);
 
+/* Batched form: several independent systems (cells with cubic grids of 24,
+ * 48, 64, 72 or 96 points, any band counts), each a block of orbitals
+ * applied to itself at q = 0: vx_out[s] = V_x[orbs[s]] orbs[s] (layout of
+ * fock_apply, leading dimension orbs[s].ld).  The band-pair work of every
+ * system runs in ONE persistent kernel (device work queue of plane, pencil
+ * and multiply-accumulate units with per-segment dependency counters), and
+ * the whole batch -- scheduler reset, orbital transforms, the persistent
+ * kernel and the per-target finish -- is captured in one hipGraph.
+ * Inputs (orbs[s].c, .w) and outputs are bound at creation; their contents
+ * may change between replays.  The plan owns its device memory.
+ * The schedule (pair-tile size, units per work ticket, persistent blocks per
+ * compute unit) is chosen by timing the candidates on this batch, unless the
+ * JSON tune cache (tune_cache, else $FOCK_TUNE_CACHE; NULL/empty: none) has
+ * an entry for the batch signature; the choice is written back to it.
+ * Creation synchronises the device (it runs the candidates). */
+fock_status fock_batch_plan_create(const fock_cell *cells, const fock_orbs *orbs, void *const *vx_out, int32_t nsys,
+                                   int32_t dtype, const char *tune_cache, void **plan);
+/* One replay of the captured graph on `stream` (asynchronous). */
+fock_status fock_batch_apply(void *plan, void *stream);
+/* Synchronises the device and reports a scheduler abort (a dependency wait
+ * that exceeded its bound) as FOCK_E_HIP. */
+fock_status fock_batch_check(void *plan);
+/* JSON description of the chosen schedule (owned by the plan). */
+const char *fock_batch_plan_info(void *plan);
+void fock_batch_plan_destroy(void *plan);
+
 /* Auxiliary: unnormalised 3-D transform of nb boxes in place (device
  * [nb][n1][n2][n3] complex of dtype); sign = -1 forward (sum e^{-iG.r}),
  * +1 backward.  The same transforms the band-pair path uses; exposed so

@@ -2,6 +2,7 @@
 // schedule (section 4 and the band-group loop split of section 5).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -855,6 +856,404 @@ fock_status kmesh_prepare(const fock_cell* cell, int32_t nk, const double* kpts,
   return get_plan(cell, dtype, plan);
 }
 
+
+// ---------------------------------------------------------------------------
+// Batched form: several systems, one persistent launch inside one hipGraph.
+// ---------------------------------------------------------------------------
+struct BatchParams {
+  int tile = 16;            // pair tile edge (<= kMacTile)
+  int slots = 6;            // pair buffers in flight (>= 4)
+  int units_per_ticket = 8;
+  int blocks_per_cu = 0;    // 0: as many as fit
+  double ms = 0.0;          // measured replay time when tuned
+};
+
+struct BatchPlanImpl {
+  int device = 0, dtype = 0, nsys = 0, cus = 0;
+  std::vector<std::shared_ptr<Plan>> plans;
+  std::vector<fock_cell> cells;
+  std::vector<fock_orbs> orbs;
+  std::vector<void*> outs;
+  std::vector<void*> phi, acc;
+  std::vector<void*> allocs;
+  double* d_k0 = nullptr;
+  double* d_gbpart = nullptr;
+  BatchSys* d_sys = nullptr;
+  BatchSeg* d_seg = nullptr;
+  void** d_slots = nullptr;
+  unsigned long long* d_ticket = nullptr;
+  int* d_done = nullptr;
+  int* d_abort = nullptr;
+  std::vector<void*> slot_mem;
+  size_t slot_bytes = 0;
+  int nseg = 0;
+  long long total_units = 0;
+  long long pairs = 0;
+  BatchParams prm;
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::string info;
+  ~BatchPlanImpl() {
+    hipSetDevice(device);
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    for (void* p : allocs) (void)hipFree(p);
+    if (cap) (void)hipStreamDestroy(cap);
+  }
+  fock_status alloc(void** p, size_t bytes) {
+    hipError_t e = hipMalloc(p, bytes > 0 ? bytes : 1);
+    if (e != hipSuccess) return fail(FOCK_E_HIP, std::string("batch allocation: ") + hipGetErrorString(e));
+    allocs.push_back(*p);
+    return FOCK_OK;
+  }
+};
+
+// Builds the unit list: system-interleaved pair tiles (per system: target tile
+// outer, occupied tile I <= J inner, the order of the single-system symmetric
+// schedule), emitted in pipelined rounds P1(r), P2(r-1), P3(r-2), MAC(r-3).
+void batch_segments(const BatchPlanImpl& B, const BatchParams& prm, std::vector<BatchSeg>* out, long long* total) {
+  struct TileRef {
+    int sys, i0, j0, ti, tj;
+  };
+  std::vector<std::vector<TileRef>> per(B.nsys);
+  for (int s = 0; s < B.nsys; ++s) {
+    const int nb = B.orbs[s].nb, T = prm.tile;
+    for (int j0 = 0; j0 < nb; j0 += T)
+      for (int i0 = 0; i0 <= j0; i0 += T)
+        per[s].push_back({s, i0, j0, std::min(T, nb - i0), std::min(T, nb - j0)});
+  }
+  std::vector<TileRef> tiles;
+  for (size_t k = 0;; ++k) {
+    bool any = false;
+    for (int s = 0; s < B.nsys; ++s)
+      if (k < per[s].size()) {
+        tiles.push_back(per[s][k]);
+        any = true;
+      }
+    if (!any) break;
+  }
+  const int nt = (int)tiles.size();
+  std::vector<int> seg_of(4 * (size_t)nt, -1);
+  std::vector<int> prev_same(nt, -1), last(B.nsys, -1);
+  for (int r = 0; r < nt; ++r) {
+    prev_same[r] = last[tiles[r].sys];
+    last[tiles[r].sys] = r;
+  }
+  out->clear();
+  long long start = 0;
+  for (int round = 0; round < nt + 3; ++round) {
+    for (int stage = 0; stage < 4; ++stage) {
+      const int r = round - stage;
+      if (r < 0 || r >= nt) continue;
+      const TileRef& t = tiles[r];
+      const Plan& P = *B.plans[t.sys];
+      const int n = P.n[0];
+      const int ngroups = n * n / pencil_columns(n, tbytes_of(B.dtype));
+      BatchSeg g{};
+      g.start = start;
+      g.sys = t.sys;
+      g.stage = stage;
+      g.slot = r % prm.slots;
+      g.i0 = t.i0;
+      g.j0 = t.j0;
+      g.ti = t.ti;
+      g.tj = t.tj;
+      g.dep[0] = g.dep[1] = -1;
+      const int tt = t.ti * t.tj;
+      switch (stage) {
+        case BS_P1:
+          g.units = tt * n;
+          if (r >= prm.slots) g.dep[0] = seg_of[4 * (r - prm.slots) + BS_MAC];
+          break;
+        case BS_P2:
+          g.units = tt * ngroups;
+          g.dep[0] = seg_of[4 * r + BS_P1];
+          break;
+        case BS_P3:
+          g.units = tt * n;
+          g.dep[0] = seg_of[4 * r + BS_P2];
+          break;
+        default:
+          g.units = (int)((P.N + kBatchW - 1) / kBatchW);
+          g.dep[0] = seg_of[4 * r + BS_P3];
+          if (prev_same[r] >= 0) g.dep[1] = seg_of[4 * prev_same[r] + BS_MAC];
+          break;
+      }
+      seg_of[4 * r + stage] = (int)out->size();
+      out->push_back(g);
+      start += g.units;
+    }
+  }
+  *total = start;
+}
+
+template <typename T>
+fock_status batch_capture(BatchPlanImpl& B, const BatchParams& prm) {
+  std::vector<BatchSeg> segs;
+  long long total = 0;
+  batch_segments(B, prm, &segs, &total);
+  B.nseg = (int)segs.size();
+  B.total_units = total;
+  // scheduler tables (re-allocated per schedule; the previous graph is dropped first)
+  if (B.exec) {
+    (void)hipGraphExecDestroy(B.exec);
+    B.exec = nullptr;
+  }
+  if (B.graph) {
+    (void)hipGraphDestroy(B.graph);
+    B.graph = nullptr;
+  }
+  fock_status st;
+  void* p = nullptr;
+  if ((st = B.alloc(&p, sizeof(BatchSeg) * segs.size())) != FOCK_OK) return st;
+  B.d_seg = static_cast<BatchSeg*>(p);
+  if ((st = B.alloc(&p, sizeof(int) * segs.size())) != FOCK_OK) return st;
+  B.d_done = static_cast<int*>(p);
+  FX_HIP(hipMemcpy(B.d_seg, segs.data(), sizeof(BatchSeg) * segs.size(), hipMemcpyHostToDevice));
+  BatchArgs a{};
+  a.sys = B.d_sys;
+  a.seg = B.d_seg;
+  a.nseg = B.nseg;
+  a.total_units = total;
+  a.units_per_ticket = prm.units_per_ticket;
+  a.slots = B.d_slots;
+  a.ticket = B.d_ticket;
+  a.done = B.d_done;
+  a.abort_flag = B.d_abort;
+  a.spin_limit = 400000000ll;  // polls of ~0.1 us each: far beyond any real wait
+  const int bpc_max = batch_blocks_per_cu<T>();
+  const int bpc = prm.blocks_per_cu > 0 && prm.blocks_per_cu < bpc_max ? prm.blocks_per_cu : bpc_max;
+  const int grid = bpc * B.cus;
+  // capture; tracing events must not enter the graph
+  Tracer& TR = tracer();
+  const bool tr_on = TR.on;
+  TR.on = false;
+  hipStream_t s = B.cap;
+  auto body = [&]() -> fock_status {
+    FX_HIP(launch_batch_reset(B.d_ticket, B.d_done, B.nseg, B.d_abort, s));
+    for (int k = 0; k < B.nsys; ++k) {
+      Engine<T> E(*B.plans[k], s);
+      fock_status st2 = E.g0_constant(&B.cells[k], true, B.d_k0 + k, B.d_gbpart);
+      if (st2 != FOCK_OK) return st2;
+      if ((st2 = E.to_real_space(B.orbs[k].c, B.orbs[k].ld, B.orbs[k].nb, B.phi[k])) != FOCK_OK) return st2;
+      FX_HIP(launch_zero<T>(B.acc[k], B.plans[k]->N * B.orbs[k].nb, s));
+    }
+    FX_HIP(launch_batch<T>(a, grid, s));
+    for (int k = 0; k < B.nsys; ++k) {
+      const Plan& P = *B.plans[k];
+      Engine<T> E(P, s);
+      const double s0 = -1.0 / (P.omega * (double)P.N * (double)P.N);
+      fock_status st2 = E.finish(B.acc[k], B.orbs[k].nb, 0, B.outs[k], B.orbs[k].ld, s0, nullptr, nullptr);
+      if (st2 != FOCK_OK) return st2;
+    }
+    return FOCK_OK;
+  };
+  hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) {
+    TR.on = tr_on;
+    return fail(FOCK_E_HIP, std::string("hipStreamBeginCapture: ") + hipGetErrorString(e));
+  }
+  st = body();
+  hipGraph_t g = nullptr;
+  e = hipStreamEndCapture(s, &g);
+  TR.on = tr_on;
+  if (st != FOCK_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return st;
+  }
+  if (e != hipSuccess) return fail(FOCK_E_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+  B.graph = g;
+  FX_HIP(hipGraphInstantiate(&B.exec, B.graph, nullptr, nullptr, 0));
+  char buf[256];
+  std::snprintf(buf, sizeof buf,
+                "{\"tile\": %d, \"slots\": %d, \"units_per_ticket\": %d, \"blocks_per_cu\": %d, \"grid\": %d, "
+                "\"segments\": %d, \"units\": %lld, \"pairs\": %lld, \"ms\": %.4f}",
+                prm.tile, prm.slots, prm.units_per_ticket, bpc, grid, B.nseg, total, B.pairs, prm.ms);
+  B.info = buf;
+  return FOCK_OK;
+}
+
+std::string batch_signature(const BatchPlanImpl& B) {
+  hipDeviceProp_t prop{};
+  (void)hipGetDeviceProperties(&prop, B.device);
+  std::string key = std::string(prop.gcnArchName) + "|cu" + std::to_string(B.cus) + "|" +
+                    (B.dtype == FOCK_C128 ? "c128" : "c64");
+  for (int k = 0; k < B.nsys; ++k)
+    key += "|" + std::to_string(B.plans[k]->n[0]) + ":" + std::to_string(B.orbs[k].nb);
+  for (char& ch : key)
+    if (ch == '"' || ch == '\\' || ch == ' ') ch = '_';
+  return key;
+}
+
+bool tune_cache_lookup(const std::string& path, const std::string& key, BatchParams* out) {
+  if (path.empty()) return false;
+  FILE* f = std::fopen(path.c_str(), "r");
+  if (!f) return false;
+  char line[4096];
+  bool found = false;
+  const std::string pat = "\"" + key + "\": {";
+  while (std::fgets(line, sizeof line, f)) {
+    const char* at = std::strstr(line, pat.c_str());
+    if (!at) continue;
+    BatchParams p;
+    if (std::sscanf(at + pat.size(), " \"tile\": %d, \"slots\": %d, \"units_per_ticket\": %d, \"blocks_per_cu\": %d, \"ms\": %lf",
+                    &p.tile, &p.slots, &p.units_per_ticket, &p.blocks_per_cu, &p.ms) == 5) {
+      *out = p;
+      found = true;
+    }
+  }
+  std::fclose(f);
+  return found;
+}
+
+void tune_cache_store(const std::string& path, const std::string& key, const BatchParams& p) {
+  if (path.empty()) return;
+  std::vector<std::string> keep;
+  if (FILE* f = std::fopen(path.c_str(), "r")) {
+    char line[4096];
+    const std::string pat = "\"" + key + "\": {";
+    while (std::fgets(line, sizeof line, f)) {
+      std::string l(line);
+      if (l.find("\": {") != std::string::npos && l.find(pat) == std::string::npos) {
+        while (!l.empty() && (l.back() == '\n' || l.back() == ',')) l.pop_back();
+        keep.push_back(l);
+      }
+    }
+    std::fclose(f);
+  }
+  char buf[512];
+  std::snprintf(buf, sizeof buf,
+                "\"%s\": {\"tile\": %d, \"slots\": %d, \"units_per_ticket\": %d, \"blocks_per_cu\": %d, \"ms\": %.4f}",
+                key.c_str(), p.tile, p.slots, p.units_per_ticket, p.blocks_per_cu, p.ms);
+  keep.push_back(buf);
+  const std::string tmp = path + ".tmp";
+  FILE* f = std::fopen(tmp.c_str(), "w");
+  if (!f) return;
+  std::fprintf(f, "{\n");
+  for (size_t k = 0; k < keep.size(); ++k) std::fprintf(f, "%s%s\n", keep[k].c_str(), k + 1 < keep.size() ? "," : "");
+  std::fprintf(f, "}\n");
+  std::fclose(f);
+  std::rename(tmp.c_str(), path.c_str());
+}
+
+template <typename T>
+fock_status batch_time(BatchPlanImpl& B, double* ms) {
+  hipEvent_t a = nullptr, b = nullptr;
+  FX_HIP(hipEventCreate(&a));
+  FX_HIP(hipEventCreate(&b));
+  hipError_t e = hipGraphLaunch(B.exec, B.cap);  // warm-up
+  if (e == hipSuccess) e = hipEventRecord(a, B.cap);
+  if (e == hipSuccess) e = hipGraphLaunch(B.exec, B.cap);
+  if (e == hipSuccess) e = hipEventRecord(b, B.cap);
+  if (e == hipSuccess) e = hipEventSynchronize(b);
+  float t = 0.0f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&t, a, b);
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (e != hipSuccess) return fail(FOCK_E_HIP, std::string("batch timing: ") + hipGetErrorString(e));
+  int aborted = 0;
+  FX_HIP(hipMemcpy(&aborted, B.d_abort, sizeof(int), hipMemcpyDeviceToHost));
+  if (aborted) return fail(FOCK_E_HIP, "batch scheduler aborted a dependency wait");
+  *ms = t;
+  return FOCK_OK;
+}
+
+// Autotuner: times the candidate schedules on this batch and keeps the fastest.
+template <typename T>
+fock_status batch_tune_and_capture(BatchPlanImpl& B, const std::string& cache) {
+  const std::string key = batch_signature(B);
+  BatchParams best;
+  const char* env = std::getenv("FOCK_BATCH_TUNE");
+  const bool tune = !(env && std::atoi(env) == 0);
+  if (tune && !tune_cache_lookup(cache, key, &best)) {
+    const int bpc_max = batch_blocks_per_cu<T>();
+    std::vector<int> bpcs = {1};
+    if (bpc_max > 1) bpcs.push_back(bpc_max);
+    double best_ms = 1e300;
+    for (int tile : {8, 16}) {
+      for (int upt : {2, 8, 32}) {
+        for (int bpc : bpcs) {
+          BatchParams p;
+          p.tile = tile;
+          p.units_per_ticket = upt;
+          p.blocks_per_cu = bpc;
+          fock_status st = batch_capture<T>(B, p);
+          if (st != FOCK_OK) return st;
+          double ms = 0.0;
+          if ((st = batch_time<T>(B, &ms)) != FOCK_OK) return st;
+          if (ms < best_ms) {
+            best_ms = ms;
+            best = p;
+            best.ms = ms;
+          }
+        }
+      }
+    }
+    tune_cache_store(cache, key, best);
+  }
+  B.prm = best;
+  return batch_capture<T>(B, best);
+}
+
+template <typename T>
+fock_status batch_create(BatchPlanImpl& B, const std::string& cache) {
+  const size_t cb = sizeof(cx<T>);
+  fock_status st;
+  void* p = nullptr;
+  long long nmax = 0;
+  for (int k = 0; k < B.nsys; ++k) {
+    const Plan& P = *B.plans[k];
+    nmax = P.N > nmax ? P.N : nmax;
+    void *ph = nullptr, *ac = nullptr;
+    if ((st = B.alloc(&ph, cb * P.N * (size_t)B.orbs[k].nb)) != FOCK_OK) return st;
+    if ((st = B.alloc(&ac, cb * P.N * (size_t)B.orbs[k].nb)) != FOCK_OK) return st;
+    B.phi.push_back(ph);
+    B.acc.push_back(ac);
+    B.pairs += (long long)B.orbs[k].nb * B.orbs[k].nb;
+  }
+  if ((st = B.alloc(&p, sizeof(double) * B.nsys)) != FOCK_OK) return st;
+  B.d_k0 = static_cast<double*>(p);
+  if ((st = B.alloc(&p, sizeof(double) * kGbParts)) != FOCK_OK) return st;
+  B.d_gbpart = static_cast<double*>(p);
+  std::vector<BatchSys> sys(B.nsys);
+  for (int k = 0; k < B.nsys; ++k) {
+    const Plan& P = *B.plans[k];
+    BatchSys& S = sys[k];
+    S.phi = B.phi[k];
+    S.acc = B.acc[k];
+    S.f = B.orbs[k].w;
+    S.tw = P.d_tw[0];
+    std::memcpy(S.kp.b, P.b, sizeof(S.kp.b));
+    S.kp.q[0] = S.kp.q[1] = S.kp.q[2] = 0.0;
+    S.kp.ecut = B.cells[k].ecut_fock;
+    S.kp.k0 = B.d_k0 + k;
+    S.kp.q_zero = 1;
+    S.N = P.N;
+    S.n = P.n[0];
+    S.nb = B.orbs[k].nb;
+    S.ngroups = P.n[1] * P.n[2] / pencil_columns(P.n[0], (int)sizeof(T));
+  }
+  if ((st = B.alloc(&p, sizeof(BatchSys) * B.nsys)) != FOCK_OK) return st;
+  B.d_sys = static_cast<BatchSys*>(p);
+  FX_HIP(hipMemcpy(B.d_sys, sys.data(), sizeof(BatchSys) * B.nsys, hipMemcpyHostToDevice));
+  // pair buffers: sized for the largest tile of the largest grid
+  const int max_slots = 6;
+  B.slot_bytes = cb * (size_t)nmax * kMacTile * kMacTile;
+  for (int k = 0; k < max_slots; ++k) {
+    if ((st = B.alloc(&p, B.slot_bytes)) != FOCK_OK) return st;
+    B.slot_mem.push_back(p);
+  }
+  if ((st = B.alloc(&p, sizeof(void*) * max_slots)) != FOCK_OK) return st;
+  B.d_slots = static_cast<void**>(p);
+  FX_HIP(hipMemcpy(B.d_slots, B.slot_mem.data(), sizeof(void*) * max_slots, hipMemcpyHostToDevice));
+  if ((st = B.alloc(&p, sizeof(unsigned long long))) != FOCK_OK) return st;
+  B.d_ticket = static_cast<unsigned long long*>(p);
+  if ((st = B.alloc(&p, sizeof(int))) != FOCK_OK) return st;
+  B.d_abort = static_cast<int*>(p);
+  FX_HIP(hipStreamCreateWithFlags(&B.cap, hipStreamNonBlocking));
+  return batch_tune_and_capture<T>(B, cache);
+}
 }  // namespace
 
 extern "C" {
@@ -971,6 +1370,74 @@ fock_status fock_fft3d(const int32_t n[3], int32_t dtype, int32_t sign, void* x,
   if (dtype == FOCK_C128) return Engine<double>(*p, s).transform(x, nb, sign);
   return Engine<float>(*p, s).transform(x, nb, sign);
 }
+
+fock_status fock_batch_plan_create(const fock_cell* cells, const fock_orbs* orbs, void* const* vx_out, int32_t nsys,
+                                   int32_t dtype, const char* tune_cache, void** plan) {
+  if (!plan) return fail(FOCK_E_ARG, "plan is NULL");
+  *plan = nullptr;
+  if (nsys <= 0 || !cells || !orbs || !vx_out) return fail(FOCK_E_ARG, "need nsys > 0, cells, orbs and vx_out");
+  if (dtype != FOCK_C128 && dtype != FOCK_C64) return fail(FOCK_E_ARG, "bad dtype");
+  auto B = std::make_unique<BatchPlanImpl>();
+  B->dtype = dtype;
+  B->nsys = nsys;
+  fock_status st;
+  for (int k = 0; k < nsys; ++k) {
+    const fock_cell* c = &cells[k];
+    if ((st = check_cell_host(c, dtype)) != FOCK_OK) return st;
+    if (!(c->n[0] == c->n[1] && c->n[1] == c->n[2]) ||
+        !(c->n[0] == 24 || c->n[0] == 48 || c->n[0] == 64 || c->n[0] == 72 || c->n[0] == 96))
+      return fail(FOCK_E_UNSUPPORTED_GRID, "batched systems need a cubic grid of 24, 48, 64, 72 or 96 points");
+    if (!grid_supported(c->n, dtype)) return fail(FOCK_E_UNSUPPORTED_GRID, "unsupported grid " + grid_str(c->n));
+    if ((st = check_orbs(&orbs[k], c->npw, "orbs[k]")) != FOCK_OK) return st;
+    if (orbs[k].nb > 0 && !vx_out[k]) return fail(FOCK_E_ARG, "vx_out[k] is NULL");
+  }
+  if (hipGetDevice(&B->device) != hipSuccess) return fail(FOCK_E_HIP, "no HIP device available");
+  hipDeviceProp_t prop{};
+  if (hipGetDeviceProperties(&prop, B->device) != hipSuccess) return fail(FOCK_E_HIP, "hipGetDeviceProperties failed");
+  B->cus = prop.multiProcessorCount;
+  for (int k = 0; k < nsys; ++k) {
+    std::shared_ptr<Plan> P;
+    if ((st = get_plan(&cells[k], dtype, &P)) != FOCK_OK) return st;
+    B->plans.push_back(P);
+    fock_cell c = cells[k];
+    c.miller = nullptr;  // host memory of the caller: not kept
+    B->cells.push_back(c);
+    B->orbs.push_back(orbs[k]);
+    B->outs.push_back(vx_out[k]);
+  }
+  const char* env_cache = std::getenv("FOCK_TUNE_CACHE");
+  const std::string cache = tune_cache ? tune_cache : (env_cache ? env_cache : "");
+  st = dtype == FOCK_C128 ? batch_create<double>(*B, cache) : batch_create<float>(*B, cache);
+  if (st != FOCK_OK) return st;
+  *plan = B.release();
+  return FOCK_OK;
+}
+
+fock_status fock_batch_apply(void* plan, void* stream) {
+  if (!plan) return fail(FOCK_E_ARG, "plan is NULL");
+  BatchPlanImpl* B = static_cast<BatchPlanImpl*>(plan);
+  hipError_t e = hipGraphLaunch(B->exec, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return fail(FOCK_E_HIP, std::string("hipGraphLaunch: ") + hipGetErrorString(e));
+  return FOCK_OK;
+}
+
+fock_status fock_batch_check(void* plan) {
+  if (!plan) return fail(FOCK_E_ARG, "plan is NULL");
+  BatchPlanImpl* B = static_cast<BatchPlanImpl*>(plan);
+  int aborted = 0;
+  hipError_t e = hipDeviceSynchronize();
+  if (e == hipSuccess) e = hipMemcpy(&aborted, B->d_abort, sizeof(int), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return fail(FOCK_E_HIP, std::string("batch check: ") + hipGetErrorString(e));
+  if (aborted) return fail(FOCK_E_HIP, "batch scheduler aborted a dependency wait");
+  return FOCK_OK;
+}
+
+const char* fock_batch_plan_info(void* plan) {
+  if (!plan) return "";
+  return static_cast<BatchPlanImpl*>(plan)->info.c_str();
+}
+
+void fock_batch_plan_destroy(void* plan) { delete static_cast<BatchPlanImpl*>(plan); }
 
 const char* fock_status_string(fock_status st) {
   switch (st) {

@@ -113,6 +113,22 @@ hipError_t launch_gb(const KernelParams& kp, const int n[3], const int nq[3], do
   return hipGetLastError();
 }
 
+// Zeroes the batch scheduler state (a kernel, so that a captured graph replays it).
+__global__ void batch_reset_kernel(unsigned long long* ticket, int* done, int nseg, int* abort_flag) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) {
+    *ticket = 0ull;
+    *abort_flag = 0;
+  }
+  for (int k = i; k < nseg; k += gridDim.x * blockDim.x) done[k] = 0;
+}
+
+hipError_t launch_batch_reset(unsigned long long* ticket, int* done, int nseg, int* abort_flag, hipStream_t s) {
+  const int blocks = (nseg + 255) / 256 > 0 ? ((nseg + 255) / 256 < 1024 ? (nseg + 255) / 256 : 1024) : 1;
+  hipLaunchKernelGGL(batch_reset_kernel, dim3(blocks), dim3(256), 0, s, ticket, done, nseg, abort_flag);
+  return hipGetLastError();
+}
+
 hipError_t launch_set_scalar(double* p, double v, hipStream_t s) {
   hipLaunchKernelGGL(set_scalar_kernel, dim3(1), dim3(64), 0, s, p, v);
   return hipGetLastError();

@@ -69,6 +69,19 @@ hipError_t launch_pencil<FX_T>(int mode, int n1, const PencilArgs& a, int nblock
 }
 
 template <>
+hipError_t launch_batch<FX_T>(const BatchArgs& a, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(batch_kernel<FX_T>, dim3(grid), dim3(kBatchW), 0, s, a);
+  return hipGetLastError();
+}
+
+template <>
+int batch_blocks_per_cu<FX_T>() {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_kernel<FX_T>, kBatchW, 0) != hipSuccess) return 1;
+  return n > 0 ? n : 1;
+}
+
+template <>
 hipError_t launch_mac_conj<FX_T>(const PlaneArgs& a, int plane, int nblocks, hipStream_t s) {
   hipLaunchKernelGGL(mac_conj_kernel<FX_T>, dim3(nblocks), dim3(256), 0, s, a, plane);
   return hipGetLastError();

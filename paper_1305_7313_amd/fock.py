@@ -85,6 +85,17 @@ def lib():
         L.fock_energy_kmesh_backward.argtypes = [P(fock_cell), ctypes.c_int32, P(ctypes.c_double), ctypes.c_int32,
                                                  P(fock_orbs), ctypes.c_void_p, P(ctypes.c_void_p),
                                                  ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
+        L.fock_batch_plan_create.restype = ctypes.c_int
+        L.fock_batch_plan_create.argtypes = [P(fock_cell), P(fock_orbs), P(ctypes.c_void_p), ctypes.c_int32,
+                                             ctypes.c_int32, ctypes.c_char_p, P(ctypes.c_void_p)]
+        L.fock_batch_apply.restype = ctypes.c_int
+        L.fock_batch_apply.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+        L.fock_batch_check.restype = ctypes.c_int
+        L.fock_batch_check.argtypes = [ctypes.c_void_p]
+        L.fock_batch_plan_info.restype = ctypes.c_char_p
+        L.fock_batch_plan_info.argtypes = [ctypes.c_void_p]
+        L.fock_batch_plan_destroy.restype = None
+        L.fock_batch_plan_destroy.argtypes = [ctypes.c_void_p]
         L.fock_fft3d.restype = ctypes.c_int
         L.fock_fft3d.argtypes = [P(ctypes.c_int32), ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
                                  ctypes.c_int32, ctypes.c_void_p]
@@ -313,3 +324,55 @@ def fock_energy_kmesh_backward(cell: Cell, kpts, C, W, grad_ex, grad, ws=None):
                                             grad_ex.data_ptr(), ptrs, ws.data_ptr(), ws.numel(),
                                             _stream(C.device)))
     return grad
+
+
+# ---------------------------------------------------------------------------
+# batched form
+# ---------------------------------------------------------------------------
+class BatchPlan:
+    """Several systems, each a block of orbitals applied to itself at q = 0,
+    in one persistent launch captured in one hipGraph (C calls:
+    fock_batch_plan_create / _apply / _check / _plan_info / _plan_destroy).
+    The tensors passed here are bound to the graph and must stay alive."""
+
+    def __init__(self, cells, coeffs, weights, outs=None, tune_cache=None):
+        import torch
+        n = len(cells)
+        if not (len(coeffs) == len(weights) == n):
+            raise ValueError("one coefficient block and one weight vector per cell")
+        dt = dtype_code(coeffs[0])
+        if outs is None:
+            outs = [torch.empty((c.shape[0], cell.npw), dtype=c.dtype, device=c.device)
+                    for c, cell in zip(coeffs, cells)]
+        self.cells, self.coeffs, self.weights, self.outs = list(cells), list(coeffs), list(weights), list(outs)
+        cs = (fock_cell * n)(*[c.c for c in self.cells])
+        os_ = (fock_orbs * n)(*[orbs(c, w) for c, w in zip(self.coeffs, self.weights)])
+        ptrs = (ctypes.c_void_p * n)(*[o.data_ptr() if o.numel() else None for o in self.outs])
+        plan = ctypes.c_void_p()
+        cache = tune_cache.encode() if tune_cache else None
+        _check(lib().fock_batch_plan_create(cs, os_, ptrs, n, dt, cache, ctypes.byref(plan)))
+        self._plan = plan
+
+    def apply(self, stream=None):
+        import torch
+        s = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream) if stream is None else stream
+        _check(lib().fock_batch_apply(self._plan, s))
+        return self.outs
+
+    def check(self):
+        _check(lib().fock_batch_check(self._plan))
+
+    def info(self) -> dict:
+        import json
+        return json.loads(lib().fock_batch_plan_info(self._plan).decode())
+
+    def close(self):
+        if getattr(self, "_plan", None) is not None and self._plan.value:
+            lib().fock_batch_plan_destroy(self._plan)
+            self._plan = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
