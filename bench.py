@@ -7,17 +7,27 @@ Coulomb kernel, backward FFT and multiply-accumulate, plus the per-orbital
 transforms and the per-target finish (all inside libfockx.so).  Inputs are
 synthetic, seeded, and resident in HBM before the timed region.
 
-Prints one JSON line.  Besides throughput it reports the dominant kernel's
-achieved bandwidth against the HBM peak (durations from HIP events recorded
-around every launch by the library's tracer, in a second pass over the same
-steps) and the CPU FP64 oracle timed on a bounded sample on the host cores.
+Default workload: 64^3 cubic cell (L = 20 bohr), 128 orbitals applied to
+themselves, FP64 (all 16384 pairs).  Next to it the same JSON line carries
+the FP32-batched vs FP64-plain comparison on the 16-system uneven batch
+(grids from {48,64,72,96}^3, 32-242 orbitals): one hipGraph replay of the
+persistent batched kernel in FP32 against per-system FP64 applies.
+
+Also reported: the dominant kernel's achieved bandwidth (its algorithmic
+bytes per launch over its average launch time, measured with HIP events the
+library records around every launch, in a second pass over the same steps)
+against the 8 TB/s HBM peak; HBM traffic from rocprofv3 counters when they
+were taken on the current kernel sources; and the CPU FP64 oracle timed on a
+bounded sample on the host cores.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import multiprocessing as mp
 import os
+import shutil
 import sys
 import time
 
@@ -30,23 +40,17 @@ import synth  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "band-pair Fock applications/sec and HBM GB/s at 1 GPU, FP32-batched vs FP64 plain"
+UNIT = "band-pair applications/s"
+MAC_TILE = 16  # pair tile edge of the library's schedules
 
 WORKLOADS = {
-    # name: (description, builder, complex dtype, bytes per complex)
-    "c2_fp64": "64^3 cubic L=20 bohr, 128 orbitals applied to themselves, FP64 (all 16384 pairs)",
+    "c2_fp64": "64^3 cubic L=20 bohr, 128 orbitals applied to themselves, FP64 (16384 pairs)",
     "c3_fp32": "96x96x128 orthorhombic 22x22x30 bohr, 512 orbitals applied to themselves, FP32 (262144 pairs)",
     "c3_fp64": "96x96x128 orthorhombic 22x22x30 bohr, 512 orbitals applied to themselves, FP64 (262144 pairs)",
+    "c4_fp32_batched": "16 systems, cubic grids from {48,64,72,96}^3, L=n/3.2, 32-242 orbitals each, FP32, "
+                       "one persistent launch in one hipGraph (451204 pairs)",
+    "c4_fp64_plain": "the same 16 systems, one FP64 fock_apply per system (451204 pairs)",
 }
-
-
-def build_workload(name):
-    if name == "c2_fp64":
-        s, c = synth.config2()
-        return s, c, "c128"
-    if name in ("c3_fp32", "c3_fp64"):
-        s, c = synth.config3()
-        return s, c, "c64" if name.endswith("fp32") else "c128"
-    raise SystemExit(f"unknown workload {name}")
 
 
 # ---------------------------------------------------------------------------
@@ -71,29 +75,227 @@ def cpu_baseline(s, c, nocc=None):
         nocc = 64 if s.n[0] * s.n[1] * s.n[2] <= 300_000 else 8
     nocc = min(nocc, c.shape[0])
     _CPU.update(s=s, c=c, nocc=nocc)
-    ctx = mp.get_context("fork")
+    ctx = mp.get_context("fork")  # forked before this process touches the GPU
     with ctx.Pool(workers) as pool:
         pool.map(abs, range(workers))  # start the workers
         t0 = time.perf_counter()
         pool.map(_cpu_worker, range(workers))
         wall = time.perf_counter() - t0
     pairs = workers * nocc
-    return {"value": pairs / wall, "unit": "band-pair applications/s", "cores": workers, "kind": "oracle",
-            "sample": f"{workers} targets x first {nocc} occupied orbitals ({pairs} pairs, FP64 scipy FFT, "
-                      f"one single-threaded process per target), wall {wall:.2f} s"}
+    return {"value": round(pairs / wall, 2), "unit": UNIT, "cores": workers, "kind": "oracle",
+            "sample": f"{workers} targets x first {nocc} occupied orbitals ({pairs} pairs) of the same workload, "
+                      f"FP64 scipy FFT, one single-threaded process per target, wall {wall:.2f} s"}
 
 
 # ---------------------------------------------------------------------------
-# algorithmic bytes per launch of the pair kernels (tile ti x tj, N points, b bytes)
+# Algorithmic bytes of each kernel class over one step (units of N*b).
+# Mirrors the library's schedules: tiles of up to 16 x 16 pairs; one orbital
+# block at q = 0 runs the pair-symmetric schedule (tiles I <= J): FP64 uses
+# the fused inverse + multiply-accumulate with a streamed mirror half, FP32
+# the parallel inverse plus one pair multiply-accumulate.
 # ---------------------------------------------------------------------------
-def kernel_bytes(cls, ti, tj, N, b):
-    if cls == "p1_pair_plane_fwd":   # read ti + tj orbital boxes, write ti*tj pair boxes
-        return (ti * tj + ti + tj) * N * b
-    if cls == "p2_pencil_kernel":    # read + write each pair box
-        return 2 * ti * tj * N * b
-    if cls == "p3_plane_inv_mac":    # read pair boxes and ti orbitals, read-modify-write tj accumulators
-        return (ti * tj + ti + 2 * tj) * N * b
-    return None
+def step_bytes(nb, N, bpc, fp64, sym=True):
+    T = min(MAC_TILE, nb)
+    acc = {}
+
+    def add(k, rd, wr, n=1):
+        a = acc.setdefault(k, [0.0, 0])
+        a[0] += (rd + wr) * N * bpc
+        a[1] += n
+
+    for j0 in range(0, nb, T):
+        tj = min(T, nb - j0)
+        for i0 in range(0, (j0 + 1) if sym else nb, T):
+            ti = min(T, nb - i0)
+            diag = sym and i0 == j0
+            add("p1_pair_plane_fwd", ti + (0 if diag else tj), ti * tj)
+            add("p2_pencil_kernel", ti * tj, ti * tj)
+            if not sym:
+                add("p3_plane_inv_mac", ti * tj + ti + tj, tj)
+            elif fp64:
+                add("p3_plane_inv_mac", ti * tj + ti + tj, tj + (0 if diag else ti * tj))
+                if not diag:
+                    add("p3_pair_mac", ti * tj + tj + ti, ti)
+            else:
+                add("p3_plane_inv_mac", ti * tj, ti * tj)
+                add("p3_pair_mac", ti * tj + ti + (0 if diag else tj) + tj + (0 if diag else ti),
+                    tj + (0 if diag else ti))
+    return acc
+
+
+def sources_sha():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1305_7313_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".h", ".hip", ".cpp")):
+            with open(os.path.join(csrc, name), "rb") as fh:
+                h.update(name.encode())
+                h.update(fh.read())
+    return h.hexdigest()
+
+
+def pmc_traffic(workload, kernel_class):
+    """HBM bytes per launch from the committed counter summary, if it was taken on these sources."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("source_sha256") != sources_sha():
+        return None
+    k = rec.get("kernels", {}).get(kernel_class)
+    if not k:
+        return None
+    return round(1024.0 * (k["fetch_kib"] * rec["fetch_scale"] + k["write_kib"] * rec["write_scale"]))
+
+
+def run_steps(step, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def traced(fock, step, steps):
+    import torch
+    fock.fock_trace_enable(True)
+    fock.fock_trace_read(reset=True)
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    tr = fock.fock_trace_read(reset=True)
+    fock.fock_trace_enable(False)
+    return tr
+
+
+def roofline(tr, acc, steps, workload):
+    pair_cls = [k for k in acc if k in tr and tr[k][1]]
+    dom = max(pair_cls, key=lambda k: tr[k][0])
+    ms, launches = tr[dom]
+    per_launch = acc[dom][0] * steps / launches
+    avg_ms = ms / launches
+    achieved = per_launch / (avg_ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": pmc_traffic(workload, dom), "kernel": dom,
+            "avg_launch_ms": round(avg_ms, 5), "bytes_per_launch": round(per_launch)}
+
+
+# ---------------------------------------------------------------------------
+# workloads
+# ---------------------------------------------------------------------------
+def single_block(name, args, cpu):
+    import torch
+    from paper_1305_7313_amd import fock
+    if name == "c2_fp64":
+        s, c = synth.config2()
+    else:
+        s, c = synth.config3()
+    fp64 = name.endswith("fp64")
+    nb, N = c.shape[0], s.n[0] * s.n[1] * s.n[2]
+    bpc = 16 if fp64 else 8
+    if cpu:
+        cpu = cpu_baseline(s, c)
+    dev = torch.device("cuda:0")
+    cdt = torch.complex128 if fp64 else torch.complex64
+    cd = torch.from_numpy(c).to(cdt).to(dev)
+    f = torch.ones(nb, dtype=torch.float64, device=dev)
+    cell = fock.Cell(s.a, s.n, s.miller)
+    out = torch.empty((nb, s.npw), dtype=cdt, device=dev)
+    ws = fock.workspace(cell, fock.dtype_code(cd), nb, nb, dev)
+
+    def step():
+        fock.fock_apply(cell, (0.0, 0.0, 0.0), cd, f, cd, out=out, ws=ws)
+
+    dt = run_steps(step, args.steps, args.warmup)
+    pairs = nb * nb
+    rec = {"value": pairs * args.steps / dt, "ms_per_step": 1e3 * dt / args.steps, "dtype": "f64" if fp64 else "f32",
+           "config": {"workload": name, "description": WORKLOADS[name], "grid": list(s.n), "npw": s.npw,
+                      "n_occ": nb, "n_tgt": nb, "pairs_per_step": pairs,
+                      "pair_symmetry": "rho_ji = conj(rho_ij) reused; pairs counted as n_occ x n_tgt"},
+           "cpu_baseline": cpu or None}
+    rec["logical_hbm_gbs"] = round(rec["value"] * 4 * N * bpc / 1e9, 1)
+    if not args.no_trace:
+        tr = traced(fock, step, args.steps)
+        acc = step_bytes(nb, N, bpc, fp64)
+        rec["roofline"] = roofline(tr, acc, args.steps, name)
+        rec["kernels"] = {k: {"ms_per_step": round(v[0] / args.steps, 4), "launches_per_step": v[1] / args.steps}
+                          for k, v in tr.items() if v[1]}
+    return rec
+
+
+def batch_inputs():
+    systems = [synth.config4_system(k) for k in range(16)]
+    return systems
+
+
+def c4_batched(args, systems, tune_cache):
+    import torch
+    from paper_1305_7313_amd import fock
+    cells, C, W = [], [], []
+    for s, c in systems:
+        cells.append(fock.Cell(s.a, s.n, s.miller))
+        C.append(torch.from_numpy(c).to(torch.complex64).cuda())
+        W.append(torch.ones(c.shape[0], dtype=torch.float64, device="cuda"))
+    t0 = time.perf_counter()
+    plan = fock.BatchPlan(cells, C, W, tune_cache=tune_cache)
+    create_s = time.perf_counter() - t0
+    dt = run_steps(plan.apply, args.batch_steps, 1)
+    plan.check()
+    pairs = sum(c.shape[0] ** 2 for _, c in systems)
+    gp = sum(c.shape[0] ** 2 * s.n[0] ** 3 for s, c in systems)
+    outs = [o.detach().to(torch.complex128) for o in plan.outs]
+    info = plan.info()
+    plan.close()
+    return {"value": pairs * args.batch_steps / dt, "ms_per_step": 1e3 * dt / args.batch_steps,
+            "gridpoint_pairs_per_s": gp * args.batch_steps / dt, "pairs_per_step": pairs,
+            "schedule": info, "plan_create_s": round(create_s, 2)}, outs
+
+
+def c4_plain64(args, systems):
+    import torch
+    from paper_1305_7313_amd import fock
+    items = []
+    for s, c in systems:
+        cell = fock.Cell(s.a, s.n, s.miller)
+        cd = torch.from_numpy(c).cuda()
+        f = torch.ones(c.shape[0], dtype=torch.float64, device="cuda")
+        out = torch.empty((c.shape[0], s.npw), dtype=torch.complex128, device="cuda")
+        ws = fock.workspace(cell, fock.FOCK_C128, c.shape[0], c.shape[0], cd.device)
+        items.append((cell, cd, f, out, ws))
+
+    def step():
+        for cell, cd, f, out, ws in items:
+            fock.fock_apply(cell, (0.0, 0.0, 0.0), cd, f, cd, out=out, ws=ws)
+
+    dt = run_steps(step, args.batch_steps, 1)
+    pairs = sum(c.shape[0] ** 2 for _, c in systems)
+    gp = sum(c.shape[0] ** 2 * s.n[0] ** 3 for s, c in systems)
+    return {"value": pairs * args.batch_steps / dt, "ms_per_step": 1e3 * dt / args.batch_steps,
+            "gridpoint_pairs_per_s": gp * args.batch_steps / dt, "pairs_per_step": pairs}, \
+        [it[3] for it in items], [it[1] for it in items]
+
+
+def batch_comparison(args, tune_cache):
+    import torch
+    systems = batch_inputs()
+    b32, outs32 = c4_batched(args, systems, tune_cache)
+    p64, outs64, coeffs = c4_plain64(args, systems)
+    num = sum(float(torch.linalg.vector_norm(a - b) ** 2) for a, b in zip(outs32, outs64))
+    den = sum(float(torch.linalg.vector_norm(b) ** 2) for b in outs64)
+    # E_x = 1/2 sum_j <psi_j | V_x psi_j> (f = 1, one block per system), FP32 batched vs FP64 plain
+    e32 = sum(0.5 * float(torch.sum(torch.conj(c) * o).real) for c, o in zip(coeffs, outs32))
+    e64 = sum(0.5 * float(torch.sum(torch.conj(c) * o).real) for c, o in zip(coeffs, outs64))
+    return {"workload": "c4", "description": WORKLOADS["c4_fp32_batched"],
+            "fp32_batched": {k: (round(v, 2) if isinstance(v, float) else v) for k, v in b32.items()},
+            "fp64_plain": {k: (round(v, 2) if isinstance(v, float) else v) for k, v in p64.items()},
+            "speedup": round(b32["value"] / p64["value"], 3),
+            "fp32_vs_fp64_vx_rel": float(np.sqrt(num / den)),
+            "fp32_vs_fp64_ex_rel": abs(e32 - e64) / abs(e64), "ex_fp64": e64}
 
 
 def main():
@@ -101,94 +303,57 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--batch-steps", type=int, default=3)
     ap.add_argument("--workload", default="c2_fp64", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-trace", action="store_true")
+    ap.add_argument("--no-compare", action="store_true", help="skip the FP32-batched vs FP64-plain comparison")
+    ap.add_argument("--tune-cache", default=os.path.join(ROOT, "gpurun_out", "fock_tune_cache.json"))
     ap.add_argument("--copy-probe", action="store_true",
-                    help="also run a plain 1 GiB device copy (bandwidth-counter calibration)")
+                    help="also run a plain device copy of known size (bandwidth-counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on one GPU only; --gpus must be 1", file=sys.stderr)
         sys.exit(2)
+    os.makedirs(os.path.dirname(args.tune_cache), exist_ok=True)
+    seed_cache = os.path.join(ROOT, "paper_1305_7313_amd", "tune_seed.json")
+    if not os.path.exists(args.tune_cache) and os.path.exists(seed_cache):
+        shutil.copyfile(seed_cache, args.tune_cache)
 
-    s, c, prec = build_workload(args.workload)
-    nb = c.shape[0]
-    N = s.n[0] * s.n[1] * s.n[2]
-    bpc = 16 if prec == "c128" else 8
-
-    cpu = None if args.no_cpu_baseline else cpu_baseline(s, c)
-
-    import torch
-    from paper_1305_7313_amd import fock
-
-    dev = torch.device("cuda:0")
-    cdt = torch.complex128 if prec == "c128" else torch.complex64
-    cd = torch.from_numpy(c).to(cdt).to(dev)
-    f = torch.ones(nb, dtype=torch.float64, device=dev)
-    cell = fock.Cell(s.a, s.n, s.miller)
-    out = torch.empty((nb, s.npw), dtype=cdt, device=dev)
-    ws = fock.workspace(cell, fock.dtype_code(cd), nb, nb, dev)
-    q = (0.0, 0.0, 0.0)
-
-    def step():
-        fock.fock_apply(cell, q, cd, f, cd, out=out, ws=ws)
-
+    wl = args.workload
+    rec = {"metric": METRIC, "unit": UNIT, "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "data": "synthetic"}
+    if wl in ("c2_fp64", "c3_fp32", "c3_fp64"):
+        r = single_block(wl, args, cpu=not args.no_cpu_baseline)
+    else:
+        import torch  # noqa: F401
+        systems = batch_inputs()
+        if wl == "c4_fp32_batched":
+            r, _ = c4_batched(args, systems, args.tune_cache)
+            r["dtype"] = "f32"
+        else:
+            r, _, _ = c4_plain64(args, systems)
+            r["dtype"] = "f64"
+        r["config"] = {"workload": wl, "description": WORKLOADS[wl], "pairs_per_step": r["pairs_per_step"]}
+        rec["steps"] = args.batch_steps
+        rec["warmup"] = 1
     if args.copy_probe:
-        src = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+        import torch
+        src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
         dst = torch.empty_like(src)
         for _ in range(3):
             dst.copy_(src)
         torch.cuda.synchronize()
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    ms_per_step = 1e3 * dt / args.steps
-    pairs = nb * nb
-    value = pairs * args.steps / dt
-
-    roof = None
-    kernels = {}
-    if not args.no_trace:
-        fock.fock_trace_enable(True)
-        fock.fock_trace_read(reset=True)
-        for _ in range(args.steps):
-            step()
-        torch.cuda.synchronize()
-        tr = fock.fock_trace_read(reset=True)
-        fock.fock_trace_enable(False)
-        kernels = {k: {"ms_per_step": v[0] / args.steps, "launches_per_step": v[1] / args.steps}
-                   for k, v in tr.items() if v[1]}
-        pair_cls = [k for k in ("p1_pair_plane_fwd", "p2_pencil_kernel", "p3_plane_inv_mac") if k in tr]
-        dom = max(pair_cls, key=lambda k: tr[k][0])
-        ti = tj = min(16, nb)
-        per_launch = kernel_bytes(dom, ti, tj, N, bpc)
-        avg_ms = tr[dom][0] / tr[dom][1]
-        achieved = per_launch / (avg_ms * 1e-3) / 1e9
-        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
-                "avg_launch_ms": round(avg_ms, 5), "bytes_per_launch": per_launch}
-
-    # whole-path logical bandwidth: 4 N b per pair (read phi_i, psi_j; read+write acc_j)
-    logical_gbs = value * 4 * N * bpc / 1e9
-    rec = {
-        "metric": METRIC, "value": round(value, 1), "unit": "band-pair applications/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64" if prec == "c128" else "f32", "data": "synthetic",
-        "config": {"workload": args.workload, "description": WORKLOADS[args.workload], "grid": list(s.n),
-                   "npw": s.npw, "n_occ": nb, "n_tgt": nb, "pairs_per_step": pairs},
-        "logical_hbm_gbs": round(logical_gbs, 1),
-        "roofline": roof,
-        "cpu_baseline": cpu,
-        "kernels": kernels,
-    }
-    print(json.dumps(rec), flush=True)
+    rec.update({k: v for k, v in r.items() if k not in ("pairs_per_step",)})
+    rec["value"] = round(rec["value"], 1)
+    rec["ms_per_step"] = round(rec["ms_per_step"], 3)
+    if not args.no_compare and wl == "c2_fp64":
+        rec["fp32_batched_vs_fp64_plain"] = batch_comparison(args, args.tune_cache)
+    order = ["metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step", "higher_is_better", "scaling",
+             "vs_baseline", "dtype", "data", "config"]
+    out = {k: rec[k] for k in order if k in rec}
+    out.update({k: v for k, v in rec.items() if k not in out})
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":
