@@ -91,8 +91,9 @@ def cpu_baseline(s, c, nocc=None):
 # Algorithmic bytes of each kernel class over one step (units of N*b).
 # Mirrors the library's schedules: tiles of up to 16 x 16 pairs; one orbital
 # block at q = 0 runs the pair-symmetric schedule (tiles I <= J): FP64 uses
-# the fused inverse + multiply-accumulate with a streamed mirror half, FP32
-# the parallel inverse plus one pair multiply-accumulate.
+# a fused inverse + multiply-accumulate for each mirror half (the transform is
+# recomputed, nothing written back), FP32 the parallel inverse plus one pair
+# multiply-accumulate.
 # ---------------------------------------------------------------------------
 def step_bytes(nb, N, bpc, fp64, sym=True):
     T = min(MAC_TILE, nb)
@@ -112,13 +113,13 @@ def step_bytes(nb, N, bpc, fp64, sym=True):
             add("p2_pencil_kernel", ti * tj, ti * tj)
             if not sym:
                 add("p3_plane_inv_mac", ti * tj + ti + tj, tj)
-            elif fp64:
-                add("p3_plane_inv_mac", ti * tj + ti + tj, tj + (0 if diag else ti * tj))
+            elif fp64:  # schedule 2: fused P3 into acc_J, fused mirror pass into acc_I
+                add("p3_plane_inv_mac", ti * tj + ti + tj, tj)
                 if not diag:
-                    add("p3_pair_mac", ti * tj + tj + ti, ti)
-            else:
+                    add("p3_second", ti * tj + tj + ti, ti)
+            else:  # schedule 1: in-place inverse, one MAC for both halves
                 add("p3_plane_inv_mac", ti * tj, ti * tj)
-                add("p3_pair_mac", ti * tj + ti + (0 if diag else tj) + tj + (0 if diag else ti),
+                add("p3_second", ti * tj + ti + (0 if diag else tj) + tj + (0 if diag else ti),
                     tj + (0 if diag else ti))
     return acc
 

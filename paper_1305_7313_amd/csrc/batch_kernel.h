@@ -57,9 +57,12 @@ struct BatchArgs {
   long long spin_limit;          // bound on polls of one dependency
 };
 
+// Multiply-accumulate of one chunk of grid points (the pair-symmetric
+// schedule's MAC, as mac_pair_kernel), the tile's occupied index taken in two
+// halves of up to 8 to bound the registers of the persistent kernel.
 template <typename T>
 __device__ __forceinline__ void batch_mac_unit(const MacArgs& A, long long p0) {
-  // same arithmetic and order as mac_pair_kernel, one point per thread
+  constexpr int H = kMacTile / 2;
   const long long N = A.N;
   const long long p = p0 + threadIdx.x;
   if (p >= N) return;
@@ -68,42 +71,44 @@ __device__ __forceinline__ void batch_mac_unit(const MacArgs& A, long long p0) {
   cx<T>* __restrict__ acc = reinterpret_cast<cx<T>*>(A.acc) + p;
   const double* __restrict__ f = A.f;
   const int ti = A.ti, tj = A.tj, mirror = A.mirror;
-  cx<T> fphi_i[kMacTile], acc_i[kMacTile];
+  for (int h0 = 0; h0 < ti; h0 += H) {
+    cx<T> fphi_i[H], acc_i[H];
 #pragma unroll
-  for (int ii = 0; ii < kMacTile; ++ii) {
-    if (ii < ti) fphi_i[ii] = cscale<T>(phi[(long long)(A.i0 + ii) * N], T(f[A.i0 + ii]));
-    acc_i[ii] = mk<T>(T(0), T(0));
-  }
-  for (int jj = 0; jj < tj; ++jj) {
-    const long long oj = (long long)(A.j0 + jj) * N;
-    const cx<T> aj0 = acc[oj];
-    const cx<T> fphi_j = cscale<T>(phi[oj], T(f[A.j0 + jj]));
-    cx<T> v[kMacTile];
+    for (int ii = 0; ii < H; ++ii) {
+      if (h0 + ii < ti) fphi_i[ii] = cscale<T>(phi[(long long)(A.i0 + h0 + ii) * N], T(f[A.i0 + h0 + ii]));
+      acc_i[ii] = mk<T>(T(0), T(0));
+    }
+    for (int jj = 0; jj < tj; ++jj) {
+      const long long oj = (long long)(A.j0 + jj) * N;
+      const cx<T> aj0 = acc[oj];
+      const cx<T> fphi_j = cscale<T>(phi[oj], T(f[A.j0 + jj]));
+      cx<T> v[H];
 #pragma unroll
-    for (int ii = 0; ii < kMacTile; ++ii)
-      if (ii < ti) v[ii] = w[(long long)(ii * tj + jj) * N];
-    T sx = aj0.x, sy = aj0.y;
+      for (int ii = 0; ii < H; ++ii)
+        if (h0 + ii < ti) v[ii] = w[(long long)((h0 + ii) * tj + jj) * N];
+      T sx = aj0.x, sy = aj0.y;
 #pragma unroll
-    for (int ii = 0; ii < kMacTile; ++ii) {
-      if (ii < ti) {
-        const cx<T> a = cmul<T>(fphi_i[ii], v[ii]);
-        sx += a.x;
-        sy += a.y;
-        if (mirror) {
-          const cx<T> m = cmulc<T>(v[ii], fphi_j);
-          acc_i[ii] = mk<T>(acc_i[ii].x + m.x, acc_i[ii].y + m.y);
+      for (int ii = 0; ii < H; ++ii) {
+        if (h0 + ii < ti) {
+          const cx<T> a = cmul<T>(fphi_i[ii], v[ii]);
+          sx += a.x;
+          sy += a.y;
+          if (mirror) {
+            const cx<T> m = cmulc<T>(v[ii], fphi_j);
+            acc_i[ii] = mk<T>(acc_i[ii].x + m.x, acc_i[ii].y + m.y);
+          }
         }
       }
+      acc[oj] = mk<T>(sx, sy);
     }
-    acc[oj] = mk<T>(sx, sy);
-  }
-  if (mirror) {
+    if (mirror) {
 #pragma unroll
-    for (int ii = 0; ii < kMacTile; ++ii) {
-      if (ii < ti) {
-        const long long oi = (long long)(A.i0 + ii) * N;
-        const cx<T> c = acc[oi];
-        acc[oi] = mk<T>(c.x + acc_i[ii].x, c.y + acc_i[ii].y);
+      for (int ii = 0; ii < H; ++ii) {
+        if (h0 + ii < ti) {
+          const long long oi = (long long)(A.i0 + h0 + ii) * N;
+          const cx<T> c = acc[oi];
+          acc[oi] = mk<T>(c.x + acc_i[ii].x, c.y + acc_i[ii].y);
+        }
       }
     }
   }
@@ -120,7 +125,7 @@ template <typename T, int NN> struct BatchShape {
 
 // Each stage body is its own (non-inlined) function so that it gets its own
 // register allocation; the dispatcher keeps only a handful of values live.
-template <typename T, int NN>
+template <typename T, int NN, int OCC>
 __device__ __noinline__ void batch_plane_unit(void* slot, const BatchSys* Sp, const BatchSeg* gp, int u,
                                               unsigned char* smem, const cx<T>* tw) {
   using Sh = BatchShape<T, NN>;
@@ -144,7 +149,7 @@ __device__ __noinline__ void batch_plane_unit(void* slot, const BatchSys* Sp, co
     plane_body<T, NN, NN, kBatchW, Sh::PSPLIT, PLANE_INV>(A, u, smem, tw, tw);
 }
 
-template <typename T, int NN>
+template <typename T, int NN, int OCC>
 __device__ __noinline__ void batch_pencil_unit(void* slot, const BatchSys* Sp, const BatchSeg* gp, int u,
                                                unsigned char* smem, const cx<T>* tw, double* red) {
   using Sh = BatchShape<T, NN>;
@@ -159,7 +164,7 @@ __device__ __noinline__ void batch_pencil_unit(void* slot, const BatchSys* Sp, c
   pencil_body<T, NN, Sh::CB, kBatchW, Sh::CSPLIT, PENCIL_FKI>(A, u, smem, tw, red);
 }
 
-template <typename T>
+template <typename T, int OCC>
 __device__ __noinline__ void batch_mac_call(void* slot, const BatchSys* Sp, const BatchSeg* gp, int u) {
   MacArgs A{};
   A.w = slot;
@@ -175,30 +180,28 @@ __device__ __noinline__ void batch_mac_call(void* slot, const BatchSys* Sp, cons
   batch_mac_unit<T>(A, (long long)u * kBatchW);
 }
 
-template <typename T, int NN>
+template <typename T, int NN, int OCC>
 __device__ __forceinline__ void batch_run_unit(const BatchArgs& B, const BatchSeg& g, const BatchSys& S, int u,
                                                unsigned char* smem, const cx<T>* tw, double* red) {
   void* slot = B.slots[g.slot];
   if (g.stage == BS_P1 || g.stage == BS_P3)
-    batch_plane_unit<T, NN>(slot, &S, &g, u, smem, tw);
+    batch_plane_unit<T, NN, OCC>(slot, &S, &g, u, smem, tw);
   else if (g.stage == BS_P2)
-    batch_pencil_unit<T, NN>(slot, &S, &g, u, smem, tw, red);
+    batch_pencil_unit<T, NN, OCC>(slot, &S, &g, u, smem, tw, red);
   else
-    batch_mac_call<T>(slot, &S, &g, u);
+    batch_mac_call<T, OCC>(slot, &S, &g, u);
 }
 
-__device__ __forceinline__ int batch_find_seg(const BatchSeg* seg, int nseg, long long unit) {
-  int lo = 0, hi = nseg - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (seg[mid].start <= unit) lo = mid;
-    else hi = mid - 1;
-  }
-  return lo;
+// Segment holding `unit`.  A block's tickets only move forward, so the search
+// starts at the block's previous segment and steps ahead.
+__device__ __forceinline__ int batch_find_seg(const BatchSeg* seg, int nseg, long long unit, int from) {
+  int g = from;
+  while (g + 1 < nseg && seg[g + 1].start <= unit) ++g;
+  return g;
 }
 
-template <typename T>
-__global__ __launch_bounds__(kBatchW, 1) void batch_kernel(BatchArgs B) {
+template <typename T, int OCC>
+__device__ __forceinline__ void batch_kernel_body(const BatchArgs& B) {
   constexpr int XB = BatchShape<T, 96>::XBYTES > BatchShape<T, 72>::XBYTES ? BatchShape<T, 96>::XBYTES
                                                                             : BatchShape<T, 72>::XBYTES;
   __shared__ __align__(16) unsigned char smem[XB];
@@ -207,6 +210,7 @@ __global__ __launch_bounds__(kBatchW, 1) void batch_kernel(BatchArgs B) {
   __shared__ long long s_first;
   __shared__ int s_go;
   int tw_n = 0;
+  int last_seg = 0;  // meaningful in thread 0 only
   const int t = threadIdx.x;
   for (;;) {
     if (t == 0) {
@@ -227,7 +231,8 @@ __global__ __launch_bounds__(kBatchW, 1) void batch_kernel(BatchArgs B) {
       // the segment of this unit, and how many of the ticket's units it covers
       __shared__ int s_seg;
       if (t == 0) {
-        const int gi = batch_find_seg(B.seg, B.nseg, unit);
+        const int gi = batch_find_seg(B.seg, B.nseg, unit, last_seg);
+        last_seg = gi;
         int go = 1;
         for (int d = 0; d < kMaxDeps && go; ++d) {
           const int dep = B.seg[gi].dep[d];
@@ -263,11 +268,11 @@ __global__ __launch_bounds__(kBatchW, 1) void batch_kernel(BatchArgs B) {
       for (long long x = unit; x < stop; ++x) {
         const int u = (int)(x - g.start);
         switch (S.n) {
-          case 24: batch_run_unit<T, 24>(B, g, S, u, smem, tw, red); break;
-          case 48: batch_run_unit<T, 48>(B, g, S, u, smem, tw, red); break;
-          case 64: batch_run_unit<T, 64>(B, g, S, u, smem, tw, red); break;
-          case 72: batch_run_unit<T, 72>(B, g, S, u, smem, tw, red); break;
-          case 96: batch_run_unit<T, 96>(B, g, S, u, smem, tw, red); break;
+          case 24: batch_run_unit<T, 24, OCC>(B, g, S, u, smem, tw, red); break;
+          case 48: batch_run_unit<T, 48, OCC>(B, g, S, u, smem, tw, red); break;
+          case 64: batch_run_unit<T, 64, OCC>(B, g, S, u, smem, tw, red); break;
+          case 72: batch_run_unit<T, 72, OCC>(B, g, S, u, smem, tw, red); break;
+          case 96: batch_run_unit<T, 96, OCC>(B, g, S, u, smem, tw, red); break;
           default: break;
         }
         __syncthreads();
@@ -281,5 +286,17 @@ __global__ __launch_bounds__(kBatchW, 1) void batch_kernel(BatchArgs B) {
   }
 }
 
+
+// Register budget variants: one persistent block per compute unit (up to 168
+// VGPRs, no spills) or two (at most 5 waves per SIMD: 96 VGPRs, some spills).
+// The autotuner times both.
+template <typename T>
+__global__ __launch_bounds__(kBatchW) void batch_kernel_occ1(BatchArgs B) {
+  batch_kernel_body<T, 1>(B);
+}
+template <typename T>
+__global__ __launch_bounds__(kBatchW) __attribute__((amdgpu_waves_per_eu(5, 8))) void batch_kernel_occ2(BatchArgs B) {
+  batch_kernel_body<T, 2>(B);
+}
 
 }  // namespace fockx

@@ -37,7 +37,7 @@ enum KClass : int {
 };
 const char* const kClassNames[KC_COUNT] = {
     "a1_scatter", "a1_pencil_inv", "a1_plane_inv", "p1_pair_plane_fwd", "p2_pencil_kernel",
-    "p2_pencil_energy", "p3_plane_inv_mac", "p3_pair_mac", "a7_plane_fwd", "a7_pencil_fwd", "a7_gather",
+    "p2_pencil_energy", "p3_plane_inv_mac", "p3_second", "a7_plane_fwd", "a7_pencil_fwd", "a7_gather",
     "reduce", "zero_fill"};
 
 struct Tracer {
@@ -475,16 +475,19 @@ struct Engine {
     return FOCK_OK;
   }
 
-  // Symmetric-schedule variant: 0 = fused inverse FFT + MAC with the mirrored
-  // half streamed afterwards (less VALU-parallel, fewer kernel phases; best
-  // for FP64), 1 = fully parallel inverse FFT then one MAC for both halves
-  // (best for FP32, whose transforms are VALU-bound).  FOCK_SYM_SCHEDULE
-  // overrides the default.
+  // Symmetric-schedule variant (FOCK_SYM_SCHEDULE overrides the default):
+  //   0  fused inverse FFT + MAC into acc_J, v_ij written back and streamed
+  //      into acc_I by a second kernel;
+  //   1  fully parallel in-place inverse FFT, then one MAC kernel for both
+  //      halves (default for FP32, whose transforms are VALU-bound);
+  //   2  fused inverse FFT + MAC into acc_J, and a second fused pass that
+  //      recomputes v_ij and accumulates the mirror into acc_I: no write-back,
+  //      one more transform (default for FP64, which is HBM-bound).
   static int sym_schedule() {
     const char* e = std::getenv("FOCK_SYM_SCHEDULE");
     const int env = e ? std::atoi(e) : -1;
-    if (env == 0 || env == 1) return env;
-    return sizeof(T) == 8 ? 0 : 1;
+    if (env >= 0 && env <= 2) return env;
+    return sizeof(T) == 8 ? 2 : 1;
   }
 
   // One band-pair job: occupied block A (real space, weights fA) against
@@ -561,6 +564,24 @@ struct Engine {
         if (J.energy) {
           FX_TRACE(KC_REDUCE);
           FX_HIP(launch_energy_tile(epart, ngroups, J.fA, J.gB, i0, j0, ti, tj, 1, J.escale, tile_e + tile, s));
+          continue;
+        }
+        if (sym_schedule() == 2) {
+          // fused inverse plane FFT + multiply-accumulate into acc_J, and for
+          // off-diagonal tiles a second fused pass that recomputes v_ij and
+          // accumulates f_j phi_j conj(v_ij) into acc_I (no write-back of v).
+          PlaneArgs lp = la;
+          lp.acc = static_cast<char*>(acc_all) + (size_t)j0 * box;
+          {
+            FX_TRACE(KC_P3);
+            FX_HIP(launch_plane<T>(PLANE_INV_MAC, P.n[1], P.n[2], lp, tj * P.n[0], s));
+          }
+          if (i0 != j0) {
+            PlaneArgs lb = lp;
+            lb.acc = static_cast<char*>(acc_all) + (size_t)i0 * box;
+            FX_TRACE(KC_P3B);
+            FX_HIP(launch_plane<T>(PLANE_INV_MAC_MIR, P.n[1], P.n[2], lb, ti * P.n[0], s));
+          }
           continue;
         }
         if (sym_schedule() == 0) {
@@ -864,7 +885,7 @@ struct BatchParams {
   int tile = 16;            // pair tile edge (<= kMacTile)
   int slots = 6;            // pair buffers in flight (>= 4)
   int units_per_ticket = 8;
-  int blocks_per_cu = 0;    // 0: as many as fit
+  int blocks_per_cu = 1;    // persistent blocks per CU (selects the register budget)
   double ms = 0.0;          // measured replay time when tuned
 };
 
@@ -1022,7 +1043,8 @@ fock_status batch_capture(BatchPlanImpl& B, const BatchParams& prm) {
   a.done = B.d_done;
   a.abort_flag = B.d_abort;
   a.spin_limit = 400000000ll;  // polls of ~0.1 us each: far beyond any real wait
-  const int bpc_max = batch_blocks_per_cu<T>();
+  const int occ = prm.blocks_per_cu >= 2 ? 2 : 1;
+  const int bpc_max = batch_blocks_per_cu<T>(occ);
   const int bpc = prm.blocks_per_cu > 0 && prm.blocks_per_cu < bpc_max ? prm.blocks_per_cu : bpc_max;
   const int grid = bpc * B.cus;
   // capture; tracing events must not enter the graph
@@ -1039,7 +1061,7 @@ fock_status batch_capture(BatchPlanImpl& B, const BatchParams& prm) {
       if ((st2 = E.to_real_space(B.orbs[k].c, B.orbs[k].ld, B.orbs[k].nb, B.phi[k])) != FOCK_OK) return st2;
       FX_HIP(launch_zero<T>(B.acc[k], B.plans[k]->N * B.orbs[k].nb, s));
     }
-    FX_HIP(launch_batch<T>(a, grid, s));
+    FX_HIP(launch_batch<T>(a, occ, grid, s));
     for (int k = 0; k < B.nsys; ++k) {
       const Plan& P = *B.plans[k];
       Engine<T> E(P, s);
@@ -1167,29 +1189,57 @@ fock_status batch_tune_and_capture(BatchPlanImpl& B, const std::string& cache) {
   const char* env = std::getenv("FOCK_BATCH_TUNE");
   const bool tune = !(env && std::atoi(env) == 0);
   if (tune && !tune_cache_lookup(cache, key, &best)) {
-    const int bpc_max = batch_blocks_per_cu<T>();
+    // greedy coordinate search over (tile, units per ticket, blocks per CU)
+    const std::vector<int> tiles = {16, 8};
+    const std::vector<int> tickets = {128, 32, 512};
     std::vector<int> bpcs = {1};
-    if (bpc_max > 1) bpcs.push_back(bpc_max);
-    double best_ms = 1e300;
-    for (int tile : {8, 16}) {
-      for (int upt : {2, 8, 32}) {
-        for (int bpc : bpcs) {
-          BatchParams p;
-          p.tile = tile;
-          p.units_per_ticket = upt;
-          p.blocks_per_cu = bpc;
-          fock_status st = batch_capture<T>(B, p);
-          if (st != FOCK_OK) return st;
+    if (batch_blocks_per_cu<T>(2) >= 2) bpcs.push_back(2);
+    std::map<std::tuple<int, int, int>, double> seen;
+    auto eval = [&](int tile, int upt, int bpc, double* ms) -> fock_status {
+      auto k = std::make_tuple(tile, upt, bpc);
+      auto it = seen.find(k);
+      if (it != seen.end()) {
+        *ms = it->second;
+        return FOCK_OK;
+      }
+      BatchParams p;
+      p.tile = tile;
+      p.units_per_ticket = upt;
+      p.blocks_per_cu = bpc;
+      fock_status st = batch_capture<T>(B, p);
+      if (st != FOCK_OK) return st;
+      if ((st = batch_time<T>(B, ms)) != FOCK_OK) return st;
+      if (const char* lg = std::getenv("FOCK_TUNE_LOG"); lg && std::atoi(lg) != 0)
+        std::fprintf(stderr, "[fock tune] tile %d ticket %d blocks/CU %d: %.3f ms\n", tile, upt, bpc, *ms);
+      seen[k] = *ms;
+      return FOCK_OK;
+    };
+    int cur[3] = {tiles[0], tickets[0], bpcs[0]};
+    double best_ms = 0.0;
+    fock_status st = eval(cur[0], cur[1], cur[2], &best_ms);
+    if (st != FOCK_OK) return st;
+    const std::vector<int>* axes[3] = {&tiles, &tickets, &bpcs};
+    for (int pass = 0; pass < 2; ++pass) {
+      bool moved = false;
+      for (int ax = 0; ax < 3; ++ax) {
+        for (int v : *axes[ax]) {
+          int trial[3] = {cur[0], cur[1], cur[2]};
+          trial[ax] = v;
           double ms = 0.0;
-          if ((st = batch_time<T>(B, &ms)) != FOCK_OK) return st;
+          if ((st = eval(trial[0], trial[1], trial[2], &ms)) != FOCK_OK) return st;
           if (ms < best_ms) {
             best_ms = ms;
-            best = p;
-            best.ms = ms;
+            cur[ax] = v;
+            moved = true;
           }
         }
       }
+      if (!moved) break;
     }
+    best.tile = cur[0];
+    best.units_per_ticket = cur[1];
+    best.blocks_per_cu = cur[2];
+    best.ms = best_ms;
     tune_cache_store(cache, key, best);
   }
   B.prm = best;

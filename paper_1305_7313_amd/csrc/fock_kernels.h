@@ -29,6 +29,7 @@ enum PlaneMode : int {
   PLANE_INV_MAC = 1,   // P3
   PLANE_FWD = 2,       // in place, forward (a7)
   PLANE_INV = 3,       // in place, backward (a1)
+  PLANE_INV_MAC_MIR = 4,  // P3, mirrored half of the pair-symmetric schedule
 };
 enum PencilMode : int {
   PENCIL_FKI = 0,  // P2: forward, kernel, backward (+ optional energy partials)
@@ -145,13 +146,21 @@ __device__ __forceinline__ void plane_body(const PlaneArgs& A, int lid, unsigned
     pass_compute<C1, -1, T>(v, tw2, t);
     cx<T>* pw = reinterpret_cast<cx<T>*>(A.w) + (long long)(ii * A.tj + jj) * N + (long long)i1 * PLANE;
     for_outputs<C1>(t, [&](int e, int row, int col) { pw[row * N3 + col] = v[e]; });
-  } else if constexpr (MODE == PLANE_INV_MAC) {
-    const int i1 = lid / A.tj, jj = lid - (lid / A.tj) * A.tj;
+  } else if constexpr (MODE == PLANE_INV_MAC || MODE == PLANE_INV_MAC_MIR) {
+    // PLANE_INV_MAC: block (jj, i1), loop over ii, acc_j += f_i phi_i v_ij.
+    // PLANE_INV_MAC_MIR (one orbital block at q = 0): block (ii, i1), loop over
+    // jj, acc_i += f_j phi_j conj(v_ij), since v_ji = conj(v_ij).
+    constexpr bool mir = MODE == PLANE_INV_MAC_MIR;
+    const int nblk = mir ? A.ti : A.tj, nloop = mir ? A.tj : A.ti;
+    const int i1 = lid / nblk, bi = lid - (lid / nblk) * nblk;
+    const int o0 = mir ? A.j0 : A.i0;
+    const cx<T>* src = reinterpret_cast<const cx<T>*>(mir ? A.bsrc : A.a);
     cx<T> s[R1::NV];
 #pragma unroll
     for (int e = 0; e < R1::NV; ++e) s[e] = mk<T>(T(0), T(0));
-    for (int ii = 0; ii < A.ti; ++ii) {
-      const cx<T>* pw = reinterpret_cast<const cx<T>*>(A.w) + (long long)(ii * A.tj + jj) * N + (long long)i1 * PLANE;
+    for (int k = 0; k < nloop; ++k) {
+      const int slot = mir ? bi * A.tj + k : k * A.tj + bi;
+      const cx<T>* pw = reinterpret_cast<const cx<T>*>(A.w) + (long long)slot * N + (long long)i1 * PLANE;
       for_inputs<C0>(t, [&](int e, int row, int col) { v[e] = pw[row * N3 + col]; });
       pass_compute<C0, +1, T>(v, tw2, t);
       exchange<C0, C1, N3, SPLIT, T>(v, smem, t);
@@ -160,18 +169,25 @@ __device__ __forceinline__ void plane_body(const PlaneArgs& A, int lid, unsigned
       pass_compute<R0, +1, T>(v, tw3, t);
       exchange<R0, R1, N3, SPLIT, T>(v, smem, t);
       pass_compute<R1, +1, T>(v, tw3, t);
-      const T fi = T(A.f[A.i0 + ii] * A.fscale);
-      const cx<T>* pa = reinterpret_cast<const cx<T>*>(A.a) + (long long)(A.i0 + ii) * N + (long long)i1 * PLANE;
-      if (A.store_v) {
+      const T fk = T(A.f[o0 + k] * A.fscale);
+      const cx<T>* pa = src + (long long)(o0 + k) * N + (long long)i1 * PLANE;
+      if (!mir && A.store_v) {
         cx<T>* pv = const_cast<cx<T>*>(pw);
         for_outputs<R1>(t, [&](int e, int row, int col) { pv[row * N3 + col] = v[e]; });
       }
-      for_outputs<R1>(t, [&](int e, int row, int col) {
-        const cx<T> pr = cmul<T>(pa[row * N3 + col], v[e]);
-        s[e] = mk<T>(s[e].x + fi * pr.x, s[e].y + fi * pr.y);
-      });
+      if constexpr (mir) {
+        for_outputs<R1>(t, [&](int e, int row, int col) {
+          const cx<T> pr = cmulc<T>(v[e], pa[row * N3 + col]);  // conj(v) phi
+          s[e] = mk<T>(s[e].x + fk * pr.x, s[e].y + fk * pr.y);
+        });
+      } else {
+        for_outputs<R1>(t, [&](int e, int row, int col) {
+          const cx<T> pr = cmul<T>(pa[row * N3 + col], v[e]);
+          s[e] = mk<T>(s[e].x + fk * pr.x, s[e].y + fk * pr.y);
+        });
+      }
     }
-    cx<T>* pc = reinterpret_cast<cx<T>*>(A.acc) + (long long)jj * N + (long long)i1 * PLANE;
+    cx<T>* pc = reinterpret_cast<cx<T>*>(A.acc) + (long long)bi * N + (long long)i1 * PLANE;
     for_outputs<R1>(t, [&](int e, int row, int col) {
       const int p = row * N3 + col;
       pc[p] = cadd<T>(pc[p], s[e]);
@@ -211,7 +227,8 @@ struct PlaneTune {
   int minb;
 };
 constexpr PlaneTune plane_tune(int tbytes, int n2, int n3, int mode) {
-  const bool pair = mode == PLANE_PAIR_FWD || mode == PLANE_INV, mac = mode == PLANE_INV_MAC;
+  const bool pair = mode == PLANE_PAIR_FWD || mode == PLANE_INV,
+             mac = mode == PLANE_INV_MAC || mode == PLANE_INV_MAC_MIR;
   if (tbytes == 8) {  // FP64
     if (n2 == 64 && n3 == 64) return pair ? PlaneTune{512, true, 2} : mac ? PlaneTune{256, false, 2} : PlaneTune{256, true, 1};
     if (n2 == 96 && n3 == 128) return pair ? PlaneTune{512, true, 1} : PlaneTune{1024, true, 1};

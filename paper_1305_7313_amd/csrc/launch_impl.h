@@ -18,6 +18,7 @@ hipError_t plane_mode(int mode, const PlaneArgs& a, int nblocks, hipStream_t s) 
     case PLANE_INV_MAC: return plane_go<PLANE_INV_MAC, N2, N3>(a, nblocks, s);
     case PLANE_FWD: return plane_go<PLANE_FWD, N2, N3>(a, nblocks, s);
     case PLANE_INV: return plane_go<PLANE_INV, N2, N3>(a, nblocks, s);
+    case PLANE_INV_MAC_MIR: return plane_go<PLANE_INV_MAC_MIR, N2, N3>(a, nblocks, s);
   }
   return hipErrorInvalidValue;
 }
@@ -69,15 +70,20 @@ hipError_t launch_pencil<FX_T>(int mode, int n1, const PencilArgs& a, int nblock
 }
 
 template <>
-hipError_t launch_batch<FX_T>(const BatchArgs& a, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(batch_kernel<FX_T>, dim3(grid), dim3(kBatchW), 0, s, a);
+hipError_t launch_batch<FX_T>(const BatchArgs& a, int occ, int grid, hipStream_t s) {
+  if (occ == 2)
+    hipLaunchKernelGGL(batch_kernel_occ2<FX_T>, dim3(grid), dim3(kBatchW), 0, s, a);
+  else
+    hipLaunchKernelGGL(batch_kernel_occ1<FX_T>, dim3(grid), dim3(kBatchW), 0, s, a);
   return hipGetLastError();
 }
 
 template <>
-int batch_blocks_per_cu<FX_T>() {
+int batch_blocks_per_cu<FX_T>(int occ) {
   int n = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_kernel<FX_T>, kBatchW, 0) != hipSuccess) return 1;
+  hipError_t e = occ == 2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_kernel_occ2<FX_T>, kBatchW, 0)
+                          : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_kernel_occ1<FX_T>, kBatchW, 0);
+  if (e != hipSuccess) return 1;
   return n > 0 ? n : 1;
 }
 
