@@ -47,6 +47,10 @@ WORKLOADS = {
     "c2_fp64": "64^3 cubic L=20 bohr, 128 orbitals applied to themselves, FP64 (16384 pairs)",
     "c3_fp32": "96x96x128 orthorhombic 22x22x30 bohr, 512 orbitals applied to themselves, FP32 (262144 pairs)",
     "c3_fp64": "96x96x128 orthorhombic 22x22x30 bohr, 512 orbitals applied to themselves, FP64 (262144 pairs)",
+    "c2r_fp64": "the c2_fp64 sphere and orbitals with the Fock cutoff at the wave-function cutoff (a quarter of "
+                "the density cutoff) on the coarser exchange grid that keeps the result exact, FP64 (16384 pairs)",
+    "c3r_fp32": "the c3_fp32 sphere and orbitals with the Fock cutoff at the wave-function cutoff on the coarser "
+                "exact exchange grid, FP32 (262144 pairs)",
     "c4_fp32_batched": "16 systems, cubic grids from {48,64,72,96}^3, L=n/3.2, 32-242 orbitals each, FP32, "
                        "one persistent launch in one hipGraph (451204 pairs)",
     "c4_fp64_plain": "the same 16 systems, one FP64 fock_apply per system (451204 pairs)",
@@ -59,24 +63,31 @@ WORKLOADS = {
 _CPU = {}
 
 
-def _cpu_worker(j):
+def _cpu_init(a, n, miller, ecut, c_occ, c_tgt):
     os.environ["OMP_NUM_THREADS"] = "1"
+    _CPU.update(a=a, n=n, miller=miller, ecut=ecut, c_occ=c_occ, c_tgt=c_tgt)
+
+
+def _cpu_worker(j):
     from oracle import exx
-    s, c, nocc = _CPU["s"], _CPU["c"], _CPU["nocc"]
+    c_occ = _CPU["c_occ"]
     t0 = time.perf_counter()
-    exx.fock_apply(s.a, s.n, s.miller, np.zeros(3), c[:nocc], np.ones(nocc), c[j:j + 1])
+    exx.fock_apply(_CPU["a"], _CPU["n"], _CPU["miller"], np.zeros(3), c_occ, np.ones(len(c_occ)),
+                   _CPU["c_tgt"][j:j + 1], ecut_fock=_CPU["ecut"])
     return time.perf_counter() - t0
 
 
-def cpu_baseline(s, c, nocc=None):
+def cpu_baseline(s, c, n=None, ecut=0.0, nocc=None):
+    n = tuple(s.n if n is None else n)
     cores = len(os.sched_getaffinity(0))
     workers = max(1, min(16, cores))
     if nocc is None:
-        nocc = 64 if s.n[0] * s.n[1] * s.n[2] <= 300_000 else 8
+        nocc = 64 if n[0] * n[1] * n[2] <= 300_000 else 8
     nocc = min(nocc, c.shape[0])
-    _CPU.update(s=s, c=c, nocc=nocc)
-    ctx = mp.get_context("fork")  # forked before this process touches the GPU
-    with ctx.Pool(workers) as pool:
+    # fresh interpreters: independent of whatever this process has initialised
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(workers, initializer=_cpu_init,
+                  initargs=(s.a, n, s.miller, ecut, c[:nocc], c[:workers])) as pool:
         pool.map(abs, range(workers))  # start the workers
         t0 = time.perf_counter()
         pool.map(_cpu_worker, range(workers))
@@ -192,20 +203,26 @@ def roofline(tr, acc, steps, workload):
 def single_block(name, args, cpu):
     import torch
     from paper_1305_7313_amd import fock
-    if name == "c2_fp64":
+    if name.startswith("c2"):
         s, c = synth.config2()
     else:
         s, c = synth.config3()
     fp64 = name.endswith("fp64")
-    nb, N = c.shape[0], s.n[0] * s.n[1] * s.n[2]
+    # reduced Fock cutoff: E_fock = E_wfc on the coarsest grid that keeps the result exact
+    ecut = s.ecut if name[2] == "r" else 0.0
+    n = tuple(s.n)
+    if ecut > 0.0:
+        n = fock.fock_exchange_grid(fock.Cell(s.a, s.n, s.miller, ecut_fock=ecut),
+                                    dtype=fock.FOCK_C128 if fp64 else fock.FOCK_C64)
+    nb, N = c.shape[0], n[0] * n[1] * n[2]
     bpc = 16 if fp64 else 8
     if cpu:
-        cpu = cpu_baseline(s, c)
+        cpu = cpu_baseline(s, c, n, ecut)
     dev = torch.device("cuda:0")
     cdt = torch.complex128 if fp64 else torch.complex64
     cd = torch.from_numpy(c).to(cdt).to(dev)
     f = torch.ones(nb, dtype=torch.float64, device=dev)
-    cell = fock.Cell(s.a, s.n, s.miller)
+    cell = fock.Cell(s.a, n, s.miller, ecut_fock=ecut)
     out = torch.empty((nb, s.npw), dtype=cdt, device=dev)
     ws = fock.workspace(cell, fock.dtype_code(cd), nb, nb, dev)
 
@@ -215,7 +232,8 @@ def single_block(name, args, cpu):
     dt = run_steps(step, args.steps, args.warmup)
     pairs = nb * nb
     rec = {"value": pairs * args.steps / dt, "ms_per_step": 1e3 * dt / args.steps, "dtype": "f64" if fp64 else "f32",
-           "config": {"workload": name, "description": WORKLOADS[name], "grid": list(s.n), "npw": s.npw,
+           "config": {"workload": name, "description": WORKLOADS[name], "grid": list(n), "npw": s.npw,
+                      "ecut_fock": ecut if ecut > 0.0 else None,
                       "n_occ": nb, "n_tgt": nb, "pairs_per_step": pairs,
                       "pair_symmetry": "rho_ji = conj(rho_ij) reused; pairs counted as n_occ x n_tgt"},
            "cpu_baseline": cpu or None}
@@ -324,7 +342,7 @@ def main():
     wl = args.workload
     rec = {"metric": METRIC, "unit": UNIT, "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "data": "synthetic"}
-    if wl in ("c2_fp64", "c3_fp32", "c3_fp64"):
+    if wl in ("c2_fp64", "c3_fp32", "c3_fp64", "c2r_fp64", "c3r_fp32"):
         r = single_block(wl, args, cpu=not args.no_cpu_baseline)
     else:
         import torch  # noqa: F401

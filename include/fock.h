@@ -66,7 +66,7 @@ typedef struct {
   double a[3][3];          /* lattice vectors a_1, a_2, a_3 as rows, bohr */
   int32_t n[3];            /* FFT grid n1 x n2 x n3; box is C order, i3 fastest */
   int32_t npw;             /* number of sphere plane waves */
-  const int32_t *miller;   /* [npw][3] signed Miller indices, |m_a| <= (n_a - 1) / 4 */
+  const int32_t *miller;   /* [npw][3] signed Miller indices; see fock_exchange_grid for the grid rule */
   double ecut_fock;        /* cutoff on |q+G|^2 (bohr^-2) for K; <= 0: whole box */
   int32_t g0;              /* fock_g0 */
   double gb_alpha;         /* FOCK_G0_GB: auxiliary width alpha, bohr^2 (> 0) */
@@ -160,6 +160,20 @@ void fock_batch_plan_destroy(void *plan);
  * +1 backward.  The same transforms the band-pair path uses; exposed so
  * they can be checked on their own. */
 fock_status fock_fft3d(const int32_t n[3], int32_t dtype, int32_t sign, void *x, int32_t nb, void *stream);
+
+/* Exchange grid for a reduced Fock cutoff (section 6: the exchange cutoff may
+ * be set below the density cutoff, four times the wave-function cutoff).
+ * Every call above requires, per axis a, with M_a the largest |m_a| of the
+ * sphere and F_a the largest |m_a| of a G with |q+G|^2 <= ecut_fock:
+ *     n_a >= min(F_a, 2 M_a) + 2 M_a + 1          (F_a unbounded if ecut_fock <= 0)
+ * and returns FOCK_E_ALIAS otherwise.  On such a grid the pair densities are
+ * exact wherever K is non-zero and V_x psi is exact on the sphere: the result
+ * does not depend on the grid.  F_a is taken as the bound
+ * (|a_a| sqrt(ecut_fock) + |a_a . q|) / (2 pi) over the nq vectors q (host,
+ * [nq][3]; nq = 0: q = 0).  Writes to n_out the compiled grid of fewest points
+ * (for dtype) that meets the rule; cell->n is not read.
+ * FOCK_E_UNSUPPORTED_GRID if no compiled grid is large enough. */
+fock_status fock_exchange_grid(const fock_cell *cell, int32_t nq, const double *q, int32_t dtype, int32_t n_out[3]);
 
 const char *fock_status_string(fock_status status);
 const char *fock_last_error(void);

@@ -79,6 +79,40 @@ def coulomb_kernel(a, n, q, ecut_fock: float = 0.0, k0: float = 0.0) -> np.ndarr
     return k
 
 
+def exchange_grid_need(a, miller, ecut_fock: float, qs=None) -> tuple:
+    """Smallest grid size per axis on which the FFT route gives the
+    grid-independent result of the reduced-cutoff exchange (section 6: the
+    Fock cutoff may be set below the density cutoff).
+
+    Pair densities have components at |m_a| <= 2 M_a (M_a: the sphere's
+    largest |m_a|).  A grid of n_a points folds the component at m_a + t n_a
+    onto m_a, so the components that K keeps (|m_a| <= F_a, the largest |m_a|
+    of the points with |q+G|^2 <= ecut_fock) are untouched when
+    n_a > F_a + 2 M_a, and phi * v (components up to M_a + min(F_a, 2 M_a))
+    lands on the sphere untouched under the same condition.  F_a here is found
+    by listing the lattice points of the ball; ecut_fock <= 0 means no cutoff.
+    """
+    a = np.asarray(a, dtype=np.float64)
+    m = np.abs(np.asarray(miller, dtype=np.int64))
+    M = m.max(axis=0)
+    if ecut_fock <= 0.0:
+        return tuple(int(4 * x + 1) for x in M)
+    b = reciprocal(a)
+    qs = np.zeros((1, 3)) if qs is None else np.asarray(qs, dtype=np.float64).reshape(-1, 3)
+    F = np.zeros(3, dtype=np.int64)
+    for q in qs:
+        # enumerate a box that surely holds the ball, then keep the ball
+        r = int(np.ceil(np.sqrt(ecut_fock) * np.linalg.norm(a, axis=1).max() / (2 * np.pi)
+                        + np.abs(a @ q).max() / (2 * np.pi))) + 1
+        ax = np.arange(-r, r + 1)
+        mm = np.stack(np.meshgrid(ax, ax, ax, indexing="ij"), axis=-1).reshape(-1, 3)
+        g = q[None, :] + mm @ b
+        inside = np.einsum("ij,ij->i", g, g) <= ecut_fock
+        if inside.any():
+            F = np.maximum(F, np.abs(mm[inside]).max(axis=0))
+    return tuple(int(min(f, 2 * x) + 2 * x + 1) for f, x in zip(F, M))
+
+
 def gb_constant(a, n, nq, alpha: float) -> float:
     """Gygi-Baldereschi value of K at q+G = 0 for a Gamma-centred nq mesh.
 

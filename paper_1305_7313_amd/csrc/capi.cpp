@@ -228,7 +228,8 @@ fock_status get_plan(const fock_cell* cell, int dtype, std::shared_ptr<Plan>* ou
       return FOCK_OK;
     }
   }
-  // Sphere checks (host only): alias-free bound and uniqueness.
+  // Sphere check (host only): every G has its own box slot.  Whether pair
+  // products alias depends on q and the cutoff: check_alias, per call.
   const long long N = (long long)cell->n[0] * cell->n[1] * cell->n[2];
   std::vector<int> slot(cell->npw);
   std::vector<unsigned char> seen((size_t)N, 0);
@@ -236,10 +237,9 @@ fock_status get_plan(const fock_cell* cell, int dtype, std::shared_ptr<Plan>* ou
     int idx[3];
     for (int k = 0; k < 3; ++k) {
       const int m = cell->miller[3 * p + k];
-      if (4 * (long long)std::abs(m) > (long long)cell->n[k] - 1) {
+      if (2 * (long long)std::abs(m) > (long long)cell->n[k] - 1) {
         char buf[160];
-        std::snprintf(buf, sizeof buf, "Miller index %d on axis %d exceeds (n-1)/4 for n=%d (pair products would alias)",
-                      m, k, cell->n[k]);
+        std::snprintf(buf, sizeof buf, "Miller index %d on axis %d does not fit the box n=%d", m, k, cell->n[k]);
         return fail(FOCK_E_ALIAS, buf);
       }
       idx[k] = (m % cell->n[k] + cell->n[k]) % cell->n[k];
@@ -729,6 +729,58 @@ fock_status check_cell_host(const fock_cell* cell, int dtype) {
   return FOCK_OK;
 }
 
+// Exactness of the pair products on the grid (reduced exchange cutoff).
+// With M_a the largest |m_a| of the sphere, a pair density has Fourier
+// components only at |m_a| <= 2 M_a, and K(q+G) is non-zero only inside the
+// ball |q+G|^2 <= E_fock, whose points have |m_a| <= F_a(q).  The grid
+// transform of the product adds to the component at m the true components at
+// m + n t (t != 0), so rho(G) is exact wherever K != 0 when
+// n_a - F_a > 2 M_a.  The product phi * v then has components up to
+// M_a + min(F_a, 2 M_a), and nothing lands on the sphere (|m_a| <= M_a) when
+// n_a > min(F_a, 2 M_a) + 2 M_a: the same condition.  F_a is bounded by
+// (|a_a| sqrt(E_fock) + |a_a . q|) / (2 pi), since m_a = a_a . (q+G) / (2 pi)
+// - a_a . q / (2 pi); without a cutoff (E_fock <= 0) F_a is unbounded and the
+// rule is n_a >= 4 M_a + 1.  need[a] receives the smallest admissible n_a.
+void alias_need(const fock_cell* cell, const double* q, int nq, int need[3]) {
+  int M[3] = {0, 0, 0};
+  for (int p = 0; p < cell->npw; ++p)
+    for (int k = 0; k < 3; ++k) {
+      const int m = std::abs(cell->miller[3 * p + k]);
+      M[k] = m > M[k] ? m : M[k];
+    }
+  for (int k = 0; k < 3; ++k) {
+    const double* ak = cell->a[k];
+    const double alen = std::sqrt(ak[0] * ak[0] + ak[1] * ak[1] + ak[2] * ak[2]);
+    long long F = 2LL * M[k];
+    if (cell->ecut_fock > 0.0) {
+      double fq = 0.0;
+      for (int j = 0; j < (nq > 0 ? nq : 1); ++j) {
+        const double* qj = nq > 0 ? q + 3 * j : nullptr;
+        const double aq = qj ? std::fabs(ak[0] * qj[0] + ak[1] * qj[1] + ak[2] * qj[2]) : 0.0;
+        fq = std::max(fq, (alen * std::sqrt(cell->ecut_fock) + aq) / (2.0 * kPi));
+      }
+      // a hair of slack so that a ball touching a lattice point counts it
+      const long long Fk = (long long)std::floor(fq + 1e-9);
+      F = std::min(F, Fk);
+    }
+    need[k] = (int)(F + 2LL * M[k] + 1);
+  }
+}
+
+fock_status check_alias(const fock_cell* cell, const double* q, int nq) {
+  int need[3];
+  alias_need(cell, q, nq, need);
+  for (int k = 0; k < 3; ++k)
+    if (cell->n[k] < need[k]) {
+      char buf[200];
+      std::snprintf(buf, sizeof buf,
+                    "grid n=%d on axis %d is below %d, the smallest without aliasing for this sphere, cutoff and q",
+                    cell->n[k], k, need[k]);
+      return fail(FOCK_E_ALIAS, buf);
+    }
+  return FOCK_OK;
+}
+
 // q + G = 0 for a non-zero q means q is a reciprocal-lattice vector:
 // its fractional coordinates a_a . q / (2 pi) are all integers.
 fock_status check_q(const fock_cell* cell, const double q[3], bool* q_zero) {
@@ -756,6 +808,7 @@ fock_status prepare(const fock_cell* cell, const double q[3], int dtype, const f
   if ((st = check_orbs(occ, cell->npw, "occ")) != FOCK_OK) return st;
   if ((st = check_orbs(tgt, cell->npw, "tgt")) != FOCK_OK) return st;
   if ((st = check_q(cell, q, &out->q_zero)) != FOCK_OK) return st;
+  if ((st = check_alias(cell, q, 1)) != FOCK_OK) return st;
   const long long N = (long long)cell->n[0] * cell->n[1] * cell->n[2];
   const int ngroups = cell->n[1] * cell->n[2] / pencil_columns(cell->n[0], tbytes_of(dtype));
   out->L = layout(N, dtype == FOCK_C128 ? 16 : 8, ngroups, occ->nb, tgt->nb);
@@ -865,6 +918,7 @@ fock_status kmesh_prepare(const fock_cell* cell, int32_t nk, const double* kpts,
                            kpts[3 * k + 2] - kpts[3 * kp + 2]};
       bool qz;
       if ((st = check_q(cell, q, &qz)) != FOCK_OK) return st;
+      if ((st = check_alias(cell, q, 1)) != FOCK_OK) return st;
     }
   const long long N = (long long)cell->n[0] * cell->n[1] * cell->n[2];
   const int ngroups = cell->n[1] * cell->n[2] / pencil_columns(cell->n[0], tbytes_of(dtype));
@@ -1421,6 +1475,44 @@ fock_status fock_fft3d(const int32_t n[3], int32_t dtype, int32_t sign, void* x,
   return Engine<float>(*p, s).transform(x, nb, sign);
 }
 
+fock_status fock_exchange_grid(const fock_cell* cell, int32_t nq, const double* q, int32_t dtype, int32_t n_out[3]) {
+  if (!cell || !n_out) return fail(FOCK_E_ARG, "cell and n_out must not be NULL");
+  if (dtype != FOCK_C128 && dtype != FOCK_C64) return fail(FOCK_E_ARG, "bad dtype");
+  if (cell->npw <= 0 || !cell->miller) return fail(FOCK_E_ARG, "empty G-sphere (npw <= 0 or miller NULL)");
+  if (nq < 0 || (nq > 0 && !q)) return fail(FOCK_E_ARG, "need nq >= 0 and q for nq > 0");
+  if (std::isnan(cell->ecut_fock)) return fail(FOCK_E_ARG, "ecut_fock is NaN");
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j)
+      if (!std::isfinite(cell->a[i][j])) return fail(FOCK_E_ARG, "lattice vectors must be finite");
+  for (int j = 0; j < 3 * nq; ++j)
+    if (!std::isfinite(q[j])) return fail(FOCK_E_ARG, "q must be finite");
+  int need[3];
+  alias_need(cell, q, nq, need);
+  static const int sizes[] = {24, 48, 64, 72, 96, 128};
+  long long best = -1;
+  int pick[3] = {0, 0, 0};
+  for (int n1 : sizes)
+    for (int n2 : sizes)
+      for (int n3 : sizes) {
+        const int n[3] = {n1, n2, n3};
+        if (n1 < need[0] || n2 < need[1] || n3 < need[2] || !grid_supported(n, dtype)) continue;
+        const long long N = (long long)n1 * n2 * n3;
+        if (best < 0 || N < best) {
+          best = N;
+          pick[0] = n1;
+          pick[1] = n2;
+          pick[2] = n3;
+        }
+      }
+  if (best < 0) {
+    char buf[160];
+    std::snprintf(buf, sizeof buf, "no compiled grid reaches %d x %d x %d", need[0], need[1], need[2]);
+    return fail(FOCK_E_UNSUPPORTED_GRID, buf);
+  }
+  for (int k = 0; k < 3; ++k) n_out[k] = pick[k];
+  return FOCK_OK;
+}
+
 fock_status fock_batch_plan_create(const fock_cell* cells, const fock_orbs* orbs, void* const* vx_out, int32_t nsys,
                                    int32_t dtype, const char* tune_cache, void** plan) {
   if (!plan) return fail(FOCK_E_ARG, "plan is NULL");
@@ -1438,6 +1530,7 @@ fock_status fock_batch_plan_create(const fock_cell* cells, const fock_orbs* orbs
         !(c->n[0] == 24 || c->n[0] == 48 || c->n[0] == 64 || c->n[0] == 72 || c->n[0] == 96))
       return fail(FOCK_E_UNSUPPORTED_GRID, "batched systems need a cubic grid of 24, 48, 64, 72 or 96 points");
     if (!grid_supported(c->n, dtype)) return fail(FOCK_E_UNSUPPORTED_GRID, "unsupported grid " + grid_str(c->n));
+    if ((st = check_alias(c, nullptr, 0)) != FOCK_OK) return st;
     if ((st = check_orbs(&orbs[k], c->npw, "orbs[k]")) != FOCK_OK) return st;
     if (orbs[k].nb > 0 && !vx_out[k]) return fail(FOCK_E_ARG, "vx_out[k] is NULL");
   }

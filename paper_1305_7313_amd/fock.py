@@ -99,6 +99,9 @@ def lib():
         L.fock_fft3d.restype = ctypes.c_int
         L.fock_fft3d.argtypes = [P(ctypes.c_int32), ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
                                  ctypes.c_int32, ctypes.c_void_p]
+        L.fock_exchange_grid.restype = ctypes.c_int
+        L.fock_exchange_grid.argtypes = [P(fock_cell), ctypes.c_int32, P(ctypes.c_double), ctypes.c_int32,
+                                         P(ctypes.c_int32)]
         L.fock_status_string.restype = ctypes.c_char_p
         L.fock_status_string.argtypes = [ctypes.c_int]
         L.fock_last_error.restype = ctypes.c_char_p
@@ -185,6 +188,17 @@ def _stream(device=None):
 
 def _qarr(q):
     return (ctypes.c_double * 3)(*[float(x) for x in q])
+
+
+def fock_exchange_grid(cell: Cell, q=None, dtype: int = FOCK_C128) -> tuple:
+    """Compiled grid of fewest points on which this sphere and cell.ecut_fock
+    give grid-independent results for every q in q ([nq, 3]; None: q = 0)
+    (C call: fock_exchange_grid; cell.n is not read)."""
+    qs = np.zeros((0, 3)) if q is None else np.ascontiguousarray(q, dtype=np.float64).reshape(-1, 3)
+    qp = qs.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if len(qs) else None
+    out = (ctypes.c_int32 * 3)()
+    _check(lib().fock_exchange_grid(ctypes.byref(cell.c), len(qs), qp, int(dtype), out))
+    return tuple(int(x) for x in out)
 
 
 def fock_workspace_size(cell: Cell, dtype: int, n_occ: int, n_tgt: int) -> int:
