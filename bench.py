@@ -51,6 +51,9 @@ WORKLOADS = {
                 "the density cutoff) on the coarser exchange grid that keeps the result exact, FP64 (16384 pairs)",
     "c3r_fp32": "the c3_fp32 sphere and orbitals with the Fock cutoff at the wave-function cutoff on the coarser "
                 "exact exchange grid, FP32 (262144 pairs)",
+    "cp_density_fp64": "band loop: charge density sum_b f_b |psi_b(r)|^2 of the 512 c3 orbitals on 96x96x128, FP64",
+    "cp_force_fp64": "band loop: force of H = -1/2 nabla^2 + V(r) on the 512 c3 orbitals on 96x96x128 "
+                     "(synthetic normal V), FP64",
     "c4_fp32_batched": "16 systems, cubic grids from {48,64,72,96}^3, L=n/3.2, 32-242 orbitals each, FP32, "
                        "one persistent launch in one hipGraph (451204 pairs)",
     "c4_fp64_plain": "the same 16 systems, one FP64 fock_apply per system (451204 pairs)",
@@ -98,6 +101,37 @@ def cpu_baseline(s, c, n=None, ecut=0.0, nocc=None):
                       f"FP64 scipy FFT, one single-threaded process per target, wall {wall:.2f} s"}
 
 
+def _band_init(a, n, miller, c, w, v, force):
+    os.environ["OMP_NUM_THREADS"] = "1"
+    _CPU.update(a=a, n=n, miller=miller, c=c, w=w, v=v, force=force)
+
+
+def _band_worker(j):
+    from oracle import bands
+    sl = slice(8 * j, 8 * j + 8)
+    t0 = time.perf_counter()
+    if _CPU["force"]:
+        bands.band_force(_CPU["a"], _CPU["n"], _CPU["miller"], np.zeros(3), _CPU["c"][sl], _CPU["w"][sl], _CPU["v"])
+    else:
+        bands.band_density(_CPU["a"], _CPU["n"], _CPU["miller"], _CPU["c"][sl], _CPU["w"][sl])
+    return time.perf_counter() - t0
+
+
+def cpu_baseline_bands(s, c, w, v, force):
+    workers = max(1, min(16, len(os.sched_getaffinity(0))))
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(workers, initializer=_band_init,
+                  initargs=(s.a, tuple(s.n), s.miller, c[:8 * workers], w[:8 * workers], v, force)) as pool:
+        pool.map(abs, range(workers))
+        t0 = time.perf_counter()
+        pool.map(_band_worker, range(workers))
+        wall = time.perf_counter() - t0
+    nb = 8 * workers
+    return {"value": round(nb / wall, 2), "unit": "bands/s", "cores": workers, "kind": "oracle",
+            "sample": f"{nb} of the workload's bands, 8 per single-threaded process, FP64 scipy FFT, "
+                      f"wall {wall:.2f} s"}
+
+
 # ---------------------------------------------------------------------------
 # Algorithmic bytes of each kernel class over one step (units of N*b).
 # Mirrors the library's schedules: tiles of up to 16 x 16 pairs; one orbital
@@ -132,6 +166,31 @@ def step_bytes(nb, N, bpc, fp64, sym=True):
                 add("p3_plane_inv_mac", ti * tj, ti * tj)
                 add("p3_second", ti * tj + ti + (0 if diag else tj) + tj + (0 if diag else ti),
                     tj + (0 if diag else ti))
+    return acc
+
+
+def band_step_bytes(nb, N, npw, bpc, force, chunk=64, groups=8):
+    """Algorithmic bytes per step of the band loops (chunks of 64 bands, 8 band
+    groups per plane), per kernel class."""
+    acc = {}
+
+    def add(k, nbytes):
+        a = acc.setdefault(k, [0.0, 0])
+        a[0] += nbytes
+        a[1] += 1
+
+    for b0 in range(0, nb, chunk):
+        n = min(chunk, nb - b0)
+        add("a1_scatter", n * N * bpc + 2 * n * npw * bpc + npw * 4)  # clear, coefficients in and out, slots
+        add("a1_pencil_inv", 2 * n * N * bpc)
+        if force:
+            add("band_plane_vmul", 2 * n * N * bpc + groups * N * bpc // 2)  # V once per band group
+            add("a7_pencil_fwd", 2 * n * N * bpc)
+            add("band_force_gather", 3 * n * npw * bpc + npw * 4)
+        else:
+            add("band_plane_density", n * N * bpc + groups * N * 8 * (2 if b0 else 1))
+    if not force:
+        add("reduce", (groups + 1) * N * 8)
     return acc
 
 
@@ -247,6 +306,44 @@ def single_block(name, args, cpu):
     return rec
 
 
+def band_loops(name, args, cpu):
+    import torch
+    from paper_1305_7313_amd import fock
+    s, c = synth.config3()
+    force = "force" in name
+    nb, N = c.shape[0], s.n[0] * s.n[1] * s.n[2]
+    w = np.full(nb, 2.0)
+    v = np.random.default_rng(20).standard_normal(s.n)
+    if cpu:
+        cpu = cpu_baseline_bands(s, c, w, v, force)
+    cd = torch.from_numpy(c).cuda()
+    wd = torch.from_numpy(w).cuda()
+    vd = torch.from_numpy(v).cuda()
+    cell = fock.Cell(s.a, s.n, s.miller)
+    ws = fock.band_workspace(cell, fock.FOCK_C128, nb, cd.device)
+    rho = torch.empty(s.n, dtype=torch.float64, device="cuda")
+    out = torch.empty_like(cd)
+
+    def step():
+        if force:
+            fock.fock_band_force(cell, (0.0, 0.0, 0.0), cd, wd, vd, out=out, ws=ws)
+        else:
+            fock.fock_band_density(cell, cd, wd, out=rho, ws=ws)
+
+    dt = run_steps(step, args.steps, args.warmup)
+    rec = {"metric": "CP band-loop bands/sec at 1 GPU", "unit": "bands/s", "value": nb * args.steps / dt,
+           "ms_per_step": 1e3 * dt / args.steps, "dtype": "f64",
+           "config": {"workload": name, "description": WORKLOADS[name], "grid": list(s.n), "npw": s.npw,
+                      "bands": nb}, "cpu_baseline": cpu or None}
+    if not args.no_trace:
+        tr = traced(fock, step, args.steps)
+        acc = band_step_bytes(nb, N, s.npw, 16, force)
+        rec["roofline"] = roofline(tr, acc, args.steps, name)
+        rec["kernels"] = {k: {"ms_per_step": round(v[0] / args.steps, 4), "launches_per_step": v[1] / args.steps}
+                          for k, v in tr.items() if v[1]}
+    return rec
+
+
 def batch_inputs():
     systems = [synth.config4_system(k) for k in range(16)]
     return systems
@@ -275,16 +372,18 @@ def c4_batched(args, systems, tune_cache):
             "schedule": info, "plan_create_s": round(create_s, 2)}, outs
 
 
-def c4_plain64(args, systems):
+def c4_plain64(args, systems, fp32=False):
+    """One fock_apply per system (FP64, or FP32 with fp32=True)."""
     import torch
     from paper_1305_7313_amd import fock
+    cdt = torch.complex64 if fp32 else torch.complex128
     items = []
     for s, c in systems:
         cell = fock.Cell(s.a, s.n, s.miller)
-        cd = torch.from_numpy(c).cuda()
+        cd = torch.from_numpy(c).to(cdt).cuda()
         f = torch.ones(c.shape[0], dtype=torch.float64, device="cuda")
-        out = torch.empty((c.shape[0], s.npw), dtype=torch.complex128, device="cuda")
-        ws = fock.workspace(cell, fock.FOCK_C128, c.shape[0], c.shape[0], cd.device)
+        out = torch.empty((c.shape[0], s.npw), dtype=cdt, device="cuda")
+        ws = fock.workspace(cell, fock.dtype_code(cd), c.shape[0], c.shape[0], cd.device)
         items.append((cell, cd, f, out, ws))
 
     def step():
@@ -304,6 +403,7 @@ def batch_comparison(args, tune_cache):
     systems = batch_inputs()
     b32, outs32 = c4_batched(args, systems, tune_cache)
     p64, outs64, coeffs = c4_plain64(args, systems)
+    p32, _, _ = c4_plain64(args, systems, fp32=True)
     num = sum(float(torch.linalg.vector_norm(a - b) ** 2) for a, b in zip(outs32, outs64))
     den = sum(float(torch.linalg.vector_norm(b) ** 2) for b in outs64)
     # E_x = 1/2 sum_j <psi_j | V_x psi_j> (f = 1, one block per system), FP32 batched vs FP64 plain
@@ -312,6 +412,7 @@ def batch_comparison(args, tune_cache):
     return {"workload": "c4", "description": WORKLOADS["c4_fp32_batched"],
             "fp32_batched": {k: (round(v, 2) if isinstance(v, float) else v) for k, v in b32.items()},
             "fp64_plain": {k: (round(v, 2) if isinstance(v, float) else v) for k, v in p64.items()},
+            "fp32_plain": {k: (round(v, 2) if isinstance(v, float) else v) for k, v in p32.items()},
             "speedup": round(b32["value"] / p64["value"], 3),
             "fp32_vs_fp64_vx_rel": float(np.sqrt(num / den)),
             "fp32_vs_fp64_ex_rel": abs(e32 - e64) / abs(e64), "ex_fp64": e64}
@@ -328,6 +429,8 @@ def main():
     ap.add_argument("--no-trace", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP32-batched vs FP64-plain comparison")
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "gpurun_out", "fock_tune_cache.json"))
+    ap.add_argument("--no-tune-seed", action="store_true",
+                    help="do not seed a missing tune cache from the committed one (forces a fresh tuning)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain device copy of known size (bandwidth-counter calibration)")
     args = ap.parse_args()
@@ -336,7 +439,7 @@ def main():
         sys.exit(2)
     os.makedirs(os.path.dirname(args.tune_cache), exist_ok=True)
     seed_cache = os.path.join(ROOT, "paper_1305_7313_amd", "tune_seed.json")
-    if not os.path.exists(args.tune_cache) and os.path.exists(seed_cache):
+    if not args.no_tune_seed and not os.path.exists(args.tune_cache) and os.path.exists(seed_cache):
         shutil.copyfile(seed_cache, args.tune_cache)
 
     wl = args.workload
@@ -344,6 +447,8 @@ def main():
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "data": "synthetic"}
     if wl in ("c2_fp64", "c3_fp32", "c3_fp64", "c2r_fp64", "c3r_fp32"):
         r = single_block(wl, args, cpu=not args.no_cpu_baseline)
+    elif wl.startswith("cp_"):
+        r = band_loops(wl, args, cpu=not args.no_cpu_baseline)
     else:
         import torch  # noqa: F401
         systems = batch_inputs()

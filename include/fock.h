@@ -161,6 +161,32 @@ void fock_batch_plan_destroy(void *plan);
  * they can be checked on their own. */
 fock_status fock_fft3d(const int32_t n[3], int32_t dtype, int32_t sign, void *x, int32_t nb, void *stream);
 
+/* Band loops of the Car-Parrinello code (section 5: the charge density and
+ * the forces on the electronic degrees of freedom are computed band by band,
+ * one 3-D FFT per band; the band index is what the band groups split).
+ * orbs.c are sphere coefficients of one k-point, orbs.w the occupations f_b;
+ * psi_b(r) = Omega^{-1/2} sum_G c_b(G) e^{iG.r} at the grid points
+ * r_m = sum_a (m_a / n_a) a_a.  Both calls take the workspace below, any grid
+ * that holds the sphere, and run on the stream in order. */
+size_t fock_band_workspace_size(const fock_cell *cell, int32_t dtype, int32_t nb);
+
+/* Charge density on the grid: rho_out[m] = sum_b f_b |psi_b(r_m)|^2, device
+ * FP64 [n1][n2][n3] (written, not accumulated), for either dtype.  Summed in
+ * a fixed order (bitwise reproducible).  cell->ecut_fock is not read. */
+fock_status fock_band_density(const fock_cell *cell, int32_t dtype, const fock_orbs *orbs, double *rho_out, void *ws,
+                              size_t ws_bytes, void *stream);
+
+/* Force of the local Hamiltonian H = -1/2 nabla^2 + V(r) on each band:
+ * force_out[b][p] = -f_b ( 1/2 |k+G_p|^2 c_b(G_p) + (V psi_b)(G_p) ), with
+ * (V psi)(G) = N^{-1} sum_m V(r_m) psi~(r_m) e^{-iG.r_m}, psi~ = sum_G c(G) e^{iG.r}
+ * (the sphere projection of V psi; -force_out is dE/dconj(c) of
+ * E = sum_b f_b <psi_b|H|psi_b>).  vloc: device real potential [n1][n2][n3]
+ * in the dtype's precision (double for FOCK_C128, float for FOCK_C64); k: the
+ * k-point (host, bohr^-1); force_out: device [orbs.nb][orbs.ld] of dtype,
+ * entries p >= npw untouched. */
+fock_status fock_band_force(const fock_cell *cell, const double k[3], int32_t dtype, const fock_orbs *orbs,
+                            const void *vloc, void *force_out, void *ws, size_t ws_bytes, void *stream);
+
 /* Exchange grid for a reduced Fock cutoff (section 6: the exchange cutoff may
  * be set below the density cutoff, four times the wave-function cutoff).
  * Every call above requires, per axis a, with M_a the largest |m_a| of the

@@ -19,7 +19,9 @@ section 4):
                       double sum), used only to pin ``exx`` on tiny inputs.
 * ``ewald``        -- Ewald lattice sums (simple-cubic Madelung constant) used
                       by the closed-form pins.
+* ``bands``        -- the band loops of the Car-Parrinello code (section 5):
+                      charge density and the force of the local Hamiltonian.
 
 Every function is FP64 NumPy/SciPy.  Pins live in ``tests/test_oracle_*.py``.
 """
-from . import exx, definitions, ewald  # noqa: F401
+from . import bands, exx, definitions, ewald  # noqa: F401

@@ -33,12 +33,12 @@ fock_status fail(fock_status s, const std::string& msg) {
 // ---------------------------------------------------------------------------
 enum KClass : int {
   KC_A1_SCATTER = 0, KC_A1_PENCIL, KC_A1_PLANE, KC_P1, KC_P2, KC_P2E, KC_P3, KC_P3B,
-  KC_A7_PLANE, KC_A7_PENCIL, KC_A7_GATHER, KC_REDUCE, KC_ZERO, KC_COUNT
+  KC_A7_PLANE, KC_A7_PENCIL, KC_A7_GATHER, KC_REDUCE, KC_ZERO, KC_BAND_DENS, KC_BAND_VMUL, KC_BAND_GATHER, KC_COUNT
 };
 const char* const kClassNames[KC_COUNT] = {
     "a1_scatter", "a1_pencil_inv", "a1_plane_inv", "p1_pair_plane_fwd", "p2_pencil_kernel",
     "p2_pencil_energy", "p3_plane_inv_mac", "p3_second", "a7_plane_fwd", "a7_pencil_fwd", "a7_gather",
-    "reduce", "zero_fill"};
+    "reduce", "zero_fill", "band_plane_density", "band_plane_vmul", "band_force_gather"};
 
 struct Tracer {
   std::mutex m;
@@ -933,6 +933,143 @@ fock_status kmesh_prepare(const fock_cell* cell, int32_t nk, const double* kpts,
 
 
 // ---------------------------------------------------------------------------
+// Band loops of the Car-Parrinello code: charge density and the force of the
+// local Hamiltonian, one 3-D transform per band, bands taken in chunks.
+// ---------------------------------------------------------------------------
+constexpr int kBandChunk = 64;   // bands per chunk of launches
+constexpr int kBandGroups = 8;   // band groups per plane: workgroups = n1 * kBandGroups
+
+struct BandLayout {
+  size_t box, part, total;
+  int cb;
+};
+
+BandLayout band_layout(long long N, int cplx_bytes, int nb) {
+  BandLayout L{};
+  L.cb = nb < kBandChunk ? (nb > 0 ? nb : 1) : kBandChunk;
+  size_t off = 0;
+  L.box = off; off += align_up((size_t)L.cb * N * cplx_bytes);
+  L.part = off; off += align_up(sizeof(double) * (size_t)kBandGroups * N);
+  L.total = off;
+  return L;
+}
+
+fock_status band_prepare(const fock_cell* cell, int32_t dtype, const fock_orbs* orbs, void* ws, size_t ws_bytes,
+                         std::shared_ptr<Plan>* plan, BandLayout* L) {
+  fock_status st = check_cell_host(cell, dtype);
+  if (st != FOCK_OK) return st;
+  if (!grid_supported(cell->n, dtype))
+    return fail(FOCK_E_UNSUPPORTED_GRID, "no compiled transforms for grid " + grid_str(cell->n));
+  if ((st = check_orbs(orbs, cell->npw, "orbs")) != FOCK_OK) return st;
+  const long long N = (long long)cell->n[0] * cell->n[1] * cell->n[2];
+  *L = band_layout(N, dtype == FOCK_C128 ? 16 : 8, orbs->nb);
+  if (!ws || ws_bytes < L->total) {
+    char buf[160];
+    std::snprintf(buf, sizeof buf, "workspace of %zu bytes is smaller than the %zu needed", ws_bytes, L->total);
+    return fail(FOCK_E_WORKSPACE, buf);
+  }
+  return get_plan(cell, dtype, plan);
+}
+
+// rho[r] = sum_b w_b |psi_b(r)|^2, psi_b(r) = Omega^{-1/2} sum_G c_b(G) e^{iG.r}
+template <typename T>
+fock_status band_density_impl(const Plan& P, const fock_orbs* o, double* rho, char* ws, const BandLayout& L,
+                              hipStream_t s) {
+  Engine<T> E(P, s);
+  void* box = ws + L.box;
+  double* part = reinterpret_cast<double*>(ws + L.part);
+  for (int b0 = 0; b0 < o->nb; b0 += L.cb) {
+    const int n = std::min(L.cb, o->nb - b0);
+    const char* c = static_cast<const char*>(o->c) + (size_t)b0 * o->ld * sizeof(cx<T>);
+    {
+      FX_TRACE(KC_A1_SCATTER);
+      FX_HIP(launch_zero<T>(box, P.N * n, s));
+      FX_HIP(launch_scatter<T>(c, o->ld, P.d_slot, P.npw, n, box, P.N, s));
+    }
+    PencilArgs pa{};
+    pa.x = box;
+    pa.tw1 = P.d_tw[0];
+    pa.N = P.N;
+    pa.n2 = P.n[1];
+    pa.n3 = P.n[2];
+    pa.count = n;
+    { FX_TRACE(KC_A1_PENCIL); FX_HIP(launch_pencil<T>(PENCIL_INV, P.n[0], pa, n * E.ngroups, s)); }
+    PlaneArgs la{};
+    la.x = box;
+    la.tw2 = P.d_tw[1];
+    la.tw3 = P.d_tw[2];
+    la.N = P.N;
+    la.n1 = P.n[0];
+    la.nb = n;
+    la.f = o->w;
+    la.i0 = b0;
+    la.fscale = 1.0 / P.omega;
+    la.ngrp = kBandGroups;
+    la.part = part;
+    la.accumulate = b0 > 0;
+    { FX_TRACE(KC_BAND_DENS); FX_HIP(launch_plane<T>(PLANE_DENS, P.n[1], P.n[2], la, P.n[0] * kBandGroups, s)); }
+  }
+  FX_TRACE(KC_REDUCE);
+  FX_HIP(launch_group_sum(part, o->nb > 0 ? kBandGroups : 0, P.N, rho, s));
+  return FOCK_OK;
+}
+
+// out_b(G) = -w_b (1/2 |k+G|^2 c_b(G) + (V psi_b)(G)),
+// (V psi)(G) = N^{-1} sum_r V(r) psi~(r) e^{-iG.r}, psi~ = sum_G c(G) e^{iG.r}
+template <typename T>
+fock_status band_force_impl(const Plan& P, const double k[3], const fock_orbs* o, const void* vloc, void* out,
+                            char* ws, const BandLayout& L, hipStream_t s) {
+  Engine<T> E(P, s);
+  void* box = ws + L.box;
+  for (int b0 = 0; b0 < o->nb; b0 += L.cb) {
+    const int n = std::min(L.cb, o->nb - b0);
+    const char* c = static_cast<const char*>(o->c) + (size_t)b0 * o->ld * sizeof(cx<T>);
+    {
+      FX_TRACE(KC_A1_SCATTER);
+      FX_HIP(launch_zero<T>(box, P.N * n, s));
+      FX_HIP(launch_scatter<T>(c, o->ld, P.d_slot, P.npw, n, box, P.N, s));
+    }
+    PencilArgs pa{};
+    pa.x = box;
+    pa.tw1 = P.d_tw[0];
+    pa.N = P.N;
+    pa.n2 = P.n[1];
+    pa.n3 = P.n[2];
+    pa.count = n;
+    { FX_TRACE(KC_A1_PENCIL); FX_HIP(launch_pencil<T>(PENCIL_INV, P.n[0], pa, n * E.ngroups, s)); }
+    PlaneArgs la{};
+    la.x = box;
+    la.tw2 = P.d_tw[1];
+    la.tw3 = P.d_tw[2];
+    la.N = P.N;
+    la.n1 = P.n[0];
+    la.nb = n;
+    la.ngrp = kBandGroups;
+    la.vloc = vloc;
+    { FX_TRACE(KC_BAND_VMUL); FX_HIP(launch_plane<T>(PLANE_VMUL, P.n[1], P.n[2], la, P.n[0] * kBandGroups, s)); }
+    { FX_TRACE(KC_A7_PENCIL); FX_HIP(launch_pencil<T>(PENCIL_FWD, P.n[0], pa, n * E.ngroups, s)); }
+    ForceArgs fa{};
+    fa.box = box;
+    fa.N = P.N;
+    fa.slot = P.d_slot;
+    fa.npw = P.npw;
+    fa.c = o->c;
+    fa.ldc = o->ld;
+    fa.out = out;
+    fa.ldo = o->ld;
+    fa.w = o->w;
+    fa.j0 = b0;
+    std::memcpy(fa.b, P.b, sizeof(fa.b));
+    for (int a = 0; a < 3; ++a) fa.k[a] = k[a];
+    fa.n1 = P.n[0];
+    fa.n2 = P.n[1];
+    fa.n3 = P.n[2];
+    { FX_TRACE(KC_BAND_GATHER); FX_HIP(launch_force_gather<T>(fa, n, s)); }
+  }
+  return FOCK_OK;
+}
+
+// ---------------------------------------------------------------------------
 // Batched form: several systems, one persistent launch inside one hipGraph.
 // ---------------------------------------------------------------------------
 struct BatchParams {
@@ -941,6 +1078,9 @@ struct BatchParams {
   int units_per_ticket = 8;
   int blocks_per_cu = 1;    // persistent blocks per CU (selects the register budget)
   double ms = 0.0;          // measured replay time when tuned
+  // 0: one persistent kernel runs every stage of every system; 1: the graph
+  // holds each system's own schedule of per-shape kernels, one after another
+  int mode = 0;
 };
 
 struct BatchPlanImpl {
@@ -965,6 +1105,8 @@ struct BatchPlanImpl {
   long long total_units = 0;
   long long pairs = 0;
   BatchParams prm;
+  void* kws = nullptr;      // mode 1: workspace of the largest system's schedule
+  size_t kws_bytes = 0;
   hipStream_t cap = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -1101,6 +1243,16 @@ fock_status batch_capture(BatchPlanImpl& B, const BatchParams& prm) {
   const int bpc_max = batch_blocks_per_cu<T>(occ);
   const int bpc = prm.blocks_per_cu > 0 && prm.blocks_per_cu < bpc_max ? prm.blocks_per_cu : bpc_max;
   const int grid = bpc * B.cus;
+  if (prm.mode == 1 && !B.kws) {
+    size_t need = 0;
+    for (int k = 0; k < B.nsys; ++k) {
+      const Plan& P = *B.plans[k];
+      const int ng = P.n[1] * P.n[2] / pencil_columns(P.n[0], (int)sizeof(T));
+      need = std::max(need, layout(P.N, (int)sizeof(cx<T>), ng, B.orbs[k].nb, B.orbs[k].nb).total);
+    }
+    if ((st = B.alloc(&B.kws, need)) != FOCK_OK) return st;
+    B.kws_bytes = need;
+  }
   // capture; tracing events must not enter the graph
   Tracer& TR = tracer();
   const bool tr_on = TR.on;
@@ -1108,6 +1260,21 @@ fock_status batch_capture(BatchPlanImpl& B, const BatchParams& prm) {
   hipStream_t s = B.cap;
   auto body = [&]() -> fock_status {
     FX_HIP(launch_batch_reset(B.d_ticket, B.d_done, B.nseg, B.d_abort, s));
+    if (prm.mode == 1) {
+      // each system's own per-shape schedule (the single-system path), in turn
+      const double q0[3] = {0.0, 0.0, 0.0};
+      for (int k = 0; k < B.nsys; ++k) {
+        const Plan& P = *B.plans[k];
+        const int ng = P.n[1] * P.n[2] / pencil_columns(P.n[0], (int)sizeof(T));
+        const Layout L = layout(P.N, (int)sizeof(cx<T>), ng, B.orbs[k].nb, B.orbs[k].nb);
+        if (L.total > B.kws_bytes) return fail(FOCK_E_WORKSPACE, "batch workspace too small");
+        const double s0 = -1.0 / (P.omega * (double)P.N * (double)P.N);
+        fock_status st2 = apply_impl<T>(&B.cells[k], P, q0, true, &B.orbs[k], &B.orbs[k],
+                                        static_cast<char*>(B.kws), L, s, B.outs[k], s0, nullptr, nullptr);
+        if (st2 != FOCK_OK) return st2;
+      }
+      return FOCK_OK;
+    }
     for (int k = 0; k < B.nsys; ++k) {
       Engine<T> E(*B.plans[k], s);
       fock_status st2 = E.g0_constant(&B.cells[k], true, B.d_k0 + k, B.d_gbpart);
@@ -1142,10 +1309,15 @@ fock_status batch_capture(BatchPlanImpl& B, const BatchParams& prm) {
   B.graph = g;
   FX_HIP(hipGraphInstantiate(&B.exec, B.graph, nullptr, nullptr, 0));
   char buf[256];
-  std::snprintf(buf, sizeof buf,
-                "{\"tile\": %d, \"slots\": %d, \"units_per_ticket\": %d, \"blocks_per_cu\": %d, \"grid\": %d, "
-                "\"segments\": %d, \"units\": %lld, \"pairs\": %lld, \"ms\": %.4f}",
-                prm.tile, prm.slots, prm.units_per_ticket, bpc, grid, B.nseg, total, B.pairs, prm.ms);
+  if (prm.mode == 1)
+    std::snprintf(buf, sizeof buf, "{\"mode\": \"kernels\", \"systems\": %d, \"pairs\": %lld, \"ms\": %.4f}",
+                  B.nsys, B.pairs, prm.ms);
+  else
+    std::snprintf(buf, sizeof buf,
+                  "{\"mode\": \"persistent\", \"tile\": %d, \"slots\": %d, \"units_per_ticket\": %d, "
+                  "\"blocks_per_cu\": %d, \"grid\": %d, \"segments\": %d, \"units\": %lld, \"pairs\": %lld, "
+                  "\"ms\": %.4f}",
+                  prm.tile, prm.slots, prm.units_per_ticket, bpc, grid, B.nseg, total, B.pairs, prm.ms);
   B.info = buf;
   return FOCK_OK;
 }
@@ -1173,8 +1345,11 @@ bool tune_cache_lookup(const std::string& path, const std::string& key, BatchPar
     const char* at = std::strstr(line, pat.c_str());
     if (!at) continue;
     BatchParams p;
-    if (std::sscanf(at + pat.size(), " \"tile\": %d, \"slots\": %d, \"units_per_ticket\": %d, \"blocks_per_cu\": %d, \"ms\": %lf",
-                    &p.tile, &p.slots, &p.units_per_ticket, &p.blocks_per_cu, &p.ms) == 5) {
+    // entries written before the mode field existed describe the persistent kernel
+    if (std::sscanf(at + pat.size(),
+                    " \"tile\": %d, \"slots\": %d, \"units_per_ticket\": %d, \"blocks_per_cu\": %d, \"ms\": %lf, "
+                    "\"mode\": %d",
+                    &p.tile, &p.slots, &p.units_per_ticket, &p.blocks_per_cu, &p.ms, &p.mode) >= 5) {
       *out = p;
       found = true;
     }
@@ -1200,8 +1375,9 @@ void tune_cache_store(const std::string& path, const std::string& key, const Bat
   }
   char buf[512];
   std::snprintf(buf, sizeof buf,
-                "\"%s\": {\"tile\": %d, \"slots\": %d, \"units_per_ticket\": %d, \"blocks_per_cu\": %d, \"ms\": %.4f}",
-                key.c_str(), p.tile, p.slots, p.units_per_ticket, p.blocks_per_cu, p.ms);
+                "\"%s\": {\"tile\": %d, \"slots\": %d, \"units_per_ticket\": %d, \"blocks_per_cu\": %d, \"ms\": %.4f, "
+                "\"mode\": %d}",
+                key.c_str(), p.tile, p.slots, p.units_per_ticket, p.blocks_per_cu, p.ms, p.mode);
   keep.push_back(buf);
   const std::string tmp = path + ".tmp";
   FILE* f = std::fopen(tmp.c_str(), "w");
@@ -1242,12 +1418,12 @@ fock_status batch_tune_and_capture(BatchPlanImpl& B, const std::string& cache) {
   BatchParams best;
   const char* env = std::getenv("FOCK_BATCH_TUNE");
   const bool tune = !(env && std::atoi(env) == 0);
-  if (tune && !tune_cache_lookup(cache, key, &best)) {
-    // greedy coordinate search over (tile, units per ticket, blocks per CU)
-    const std::vector<int> tiles = {16, 8};
-    const std::vector<int> tickets = {128, 32, 512};
-    std::vector<int> bpcs = {1};
-    if (batch_blocks_per_cu<T>(2) >= 2) bpcs.push_back(2);
+  // FOCK_BATCH_MODE = 0 / 1 restricts the plan to one mode (no cache use)
+  const char* me = std::getenv("FOCK_BATCH_MODE");
+  const int force_mode = me && (std::atoi(me) == 0 || std::atoi(me) == 1) ? std::atoi(me) : -1;
+  if (!tune) {
+    best.mode = force_mode == 1 ? 1 : 0;
+  } else if (force_mode >= 0 || !tune_cache_lookup(cache, key, &best)) {
     std::map<std::tuple<int, int, int>, double> seen;
     auto eval = [&](int tile, int upt, int bpc, double* ms) -> fock_status {
       auto k = std::make_tuple(tile, upt, bpc);
@@ -1268,33 +1444,55 @@ fock_status batch_tune_and_capture(BatchPlanImpl& B, const std::string& cache) {
       seen[k] = *ms;
       return FOCK_OK;
     };
-    int cur[3] = {tiles[0], tickets[0], bpcs[0]};
-    double best_ms = 0.0;
-    fock_status st = eval(cur[0], cur[1], cur[2], &best_ms);
-    if (st != FOCK_OK) return st;
-    const std::vector<int>* axes[3] = {&tiles, &tickets, &bpcs};
-    for (int pass = 0; pass < 2; ++pass) {
-      bool moved = false;
-      for (int ax = 0; ax < 3; ++ax) {
-        for (int v : *axes[ax]) {
-          int trial[3] = {cur[0], cur[1], cur[2]};
-          trial[ax] = v;
-          double ms = 0.0;
-          if ((st = eval(trial[0], trial[1], trial[2], &ms)) != FOCK_OK) return st;
-          if (ms < best_ms) {
-            best_ms = ms;
-            cur[ax] = v;
-            moved = true;
+    fock_status st;
+    double best_ms = -1.0;
+    if (force_mode != 1) {
+      // persistent kernel: greedy coordinate search over (tile, units per ticket, blocks per CU)
+      const std::vector<int> tiles = {16, 8};
+      const std::vector<int> tickets = {128, 32, 512};
+      std::vector<int> bpcs = {1};
+      if (batch_blocks_per_cu<T>(2) >= 2) bpcs.push_back(2);
+      int cur[3] = {tiles[0], tickets[0], bpcs[0]};
+      if ((st = eval(cur[0], cur[1], cur[2], &best_ms)) != FOCK_OK) return st;
+      const std::vector<int>* axes[3] = {&tiles, &tickets, &bpcs};
+      for (int pass = 0; pass < 2; ++pass) {
+        bool moved = false;
+        for (int ax = 0; ax < 3; ++ax) {
+          for (int v : *axes[ax]) {
+            int trial[3] = {cur[0], cur[1], cur[2]};
+            trial[ax] = v;
+            double ms = 0.0;
+            if ((st = eval(trial[0], trial[1], trial[2], &ms)) != FOCK_OK) return st;
+            if (ms < best_ms) {
+              best_ms = ms;
+              cur[ax] = v;
+              moved = true;
+            }
           }
         }
+        if (!moved) break;
       }
-      if (!moved) break;
+      best.tile = cur[0];
+      best.units_per_ticket = cur[1];
+      best.blocks_per_cu = cur[2];
+      best.ms = best_ms;
+      best.mode = 0;
     }
-    best.tile = cur[0];
-    best.units_per_ticket = cur[1];
-    best.blocks_per_cu = cur[2];
-    best.ms = best_ms;
-    tune_cache_store(cache, key, best);
+    if (force_mode != 0) {
+      // the per-shape kernels of every system in one graph
+      BatchParams p;
+      p.mode = 1;
+      double ms = 0.0;
+      if ((st = batch_capture<T>(B, p)) != FOCK_OK) return st;
+      if ((st = batch_time<T>(B, &ms)) != FOCK_OK) return st;
+      if (const char* lg = std::getenv("FOCK_TUNE_LOG"); lg && std::atoi(lg) != 0)
+        std::fprintf(stderr, "[fock tune] per-shape kernels: %.3f ms\n", ms);
+      if (best_ms < 0.0 || ms < best_ms) {
+        best = p;
+        best.ms = ms;
+      }
+    }
+    if (force_mode < 0) tune_cache_store(cache, key, best);
   }
   B.prm = best;
   return batch_capture<T>(B, best);
@@ -1473,6 +1671,42 @@ fock_status fock_fft3d(const int32_t n[3], int32_t dtype, int32_t sign, void* x,
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (dtype == FOCK_C128) return Engine<double>(*p, s).transform(x, nb, sign);
   return Engine<float>(*p, s).transform(x, nb, sign);
+}
+
+size_t fock_band_workspace_size(const fock_cell* cell, int32_t dtype, int32_t nb) {
+  if (!cell || nb < 0 || (dtype != FOCK_C128 && dtype != FOCK_C64)) return 0;
+  if (!grid_supported(cell->n, dtype)) return 0;
+  const long long N = (long long)cell->n[0] * cell->n[1] * cell->n[2];
+  return band_layout(N, dtype == FOCK_C128 ? 16 : 8, nb).total;
+}
+
+fock_status fock_band_density(const fock_cell* cell, int32_t dtype, const fock_orbs* orbs, double* rho_out, void* ws,
+                              size_t ws_bytes, void* stream) {
+  std::shared_ptr<Plan> P;
+  BandLayout L;
+  fock_status st = band_prepare(cell, dtype, orbs, ws, ws_bytes, &P, &L);
+  if (st != FOCK_OK) return st;
+  if (!rho_out) return fail(FOCK_E_ARG, "rho_out is NULL");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  char* w = static_cast<char*>(ws);
+  if (dtype == FOCK_C128) return band_density_impl<double>(*P, orbs, rho_out, w, L, s);
+  return band_density_impl<float>(*P, orbs, rho_out, w, L, s);
+}
+
+fock_status fock_band_force(const fock_cell* cell, const double k[3], int32_t dtype, const fock_orbs* orbs,
+                            const void* vloc, void* force_out, void* ws, size_t ws_bytes, void* stream) {
+  if (!k) return fail(FOCK_E_ARG, "k is NULL");
+  for (int a = 0; a < 3; ++a)
+    if (!std::isfinite(k[a])) return fail(FOCK_E_ARG, "k must be finite");
+  std::shared_ptr<Plan> P;
+  BandLayout L;
+  fock_status st = band_prepare(cell, dtype, orbs, ws, ws_bytes, &P, &L);
+  if (st != FOCK_OK) return st;
+  if (orbs->nb > 0 && (!vloc || !force_out)) return fail(FOCK_E_ARG, "vloc and force_out must not be NULL");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  char* w = static_cast<char*>(ws);
+  if (dtype == FOCK_C128) return band_force_impl<double>(*P, k, orbs, vloc, force_out, w, L, s);
+  return band_force_impl<float>(*P, k, orbs, vloc, force_out, w, L, s);
 }
 
 fock_status fock_exchange_grid(const fock_cell* cell, int32_t nq, const double* q, int32_t dtype, int32_t n_out[3]) {

@@ -30,6 +30,8 @@ enum PlaneMode : int {
   PLANE_FWD = 2,       // in place, forward (a7)
   PLANE_INV = 3,       // in place, backward (a1)
   PLANE_INV_MAC_MIR = 4,  // P3, mirrored half of the pair-symmetric schedule
+  PLANE_DENS = 5,      // band loop: backward plane FFT, accumulate w |psi|^2
+  PLANE_VMUL = 6,      // band loop, in place: backward plane FFT, x V(r), forward plane FFT
 };
 enum PencilMode : int {
   PENCIL_FKI = 0,  // P2: forward, kernel, backward (+ optional energy partials)
@@ -61,6 +63,12 @@ struct PlaneArgs {
   int n1, nb;
   double fscale;       // constant factor on f in P3
   int store_v;         // P3: also write the real-space v back into the pair buffer
+  // band loops (PLANE_DENS, PLANE_VMUL): workgroup (i1, group g) takes the
+  // bands g, g + ngrp, ... < nb of x
+  int ngrp;
+  double* part;        // PLANE_DENS: FP64 partial densities [ngrp][N]
+  int accumulate;      // PLANE_DENS: add to part (else overwrite)
+  const void* vloc;    // PLANE_VMUL: real potential V(r) [N], path precision
 };
 
 struct PencilArgs {
@@ -204,6 +212,60 @@ __device__ __forceinline__ void plane_body(const PlaneArgs& A, int lid, unsigned
     exchange<C0, C1, N3, SPLIT, T>(v, smem, t);
     pass_compute<C1, -1, T>(v, tw2, t);
     for_outputs<C1>(t, [&](int e, int row, int col) { px[row * N3 + col] = v[e]; });
+  } else if constexpr (MODE == PLANE_DENS) {
+    // sum over this group's bands of f_b * fscale * |psi_b(r)|^2 on plane i1
+    const int G = A.ngrp;
+    const int i1 = lid / G, g = lid - (lid / G) * G;
+    T acc[R1::NV];
+#pragma unroll
+    for (int e = 0; e < R1::NV; ++e) acc[e] = T(0);
+    for (int b = g; b < A.nb; b += G) {
+      const cx<T>* px = reinterpret_cast<const cx<T>*>(A.x) + (long long)b * N + (long long)i1 * PLANE;
+      for_inputs<C0>(t, [&](int e, int row, int col) { v[e] = px[row * N3 + col]; });
+      pass_compute<C0, +1, T>(v, tw2, t);
+      exchange<C0, C1, N3, SPLIT, T>(v, smem, t);
+      pass_compute<C1, +1, T>(v, tw2, t);
+      exchange<C1, R0, N3, SPLIT, T>(v, smem, t);
+      pass_compute<R0, +1, T>(v, tw3, t);
+      exchange<R0, R1, N3, SPLIT, T>(v, smem, t);
+      pass_compute<R1, +1, T>(v, tw3, t);
+      const T wb = T(A.f[A.i0 + b] * A.fscale);
+      for_outputs<R1>(t, [&](int e, int row, int col) { acc[e] += wb * (v[e].x * v[e].x + v[e].y * v[e].y); });
+    }
+    double* pp = A.part + (long long)g * N + (long long)i1 * PLANE;
+    for_outputs<R1>(t, [&](int e, int row, int col) {
+      const int p = row * N3 + col;
+      pp[p] = (A.accumulate ? pp[p] : 0.0) + double(acc[e]);
+    });
+  } else if constexpr (MODE == PLANE_VMUL) {
+    // psi_b(i1, r2, r3) = backward plane FFT; times V(r); forward plane FFT
+    // back into place.  V's plane stays in registers for the group's bands.
+    const int G = A.ngrp;
+    const int i1 = lid / G, g = lid - (lid / G) * G;
+    const T* pv = reinterpret_cast<const T*>(A.vloc) + (long long)i1 * PLANE;
+    T vr[R1::NV];
+    for_outputs<R1>(t, [&](int e, int row, int col) { vr[e] = pv[row * N3 + col]; });
+    for (int b = g; b < A.nb; b += G) {
+      cx<T>* px = reinterpret_cast<cx<T>*>(A.x) + (long long)b * N + (long long)i1 * PLANE;
+      for_inputs<C0>(t, [&](int e, int row, int col) { v[e] = px[row * N3 + col]; });
+      pass_compute<C0, +1, T>(v, tw2, t);
+      exchange<C0, C1, N3, SPLIT, T>(v, smem, t);
+      pass_compute<C1, +1, T>(v, tw2, t);
+      exchange<C1, R0, N3, SPLIT, T>(v, smem, t);
+      pass_compute<R0, +1, T>(v, tw3, t);
+      exchange<R0, R1, N3, SPLIT, T>(v, smem, t);
+      pass_compute<R1, +1, T>(v, tw3, t);
+      for_outputs<R1>(t, [&](int e, int row, int col) { v[e] = cscale<T>(v[e], vr[e]); });
+      exchange<R1, R0, N3, SPLIT, T>(v, smem, t);
+      pass_compute<R0, -1, T>(v, tw3, t);
+      exchange<R0, R1, N3, SPLIT, T>(v, smem, t);
+      pass_compute<R1, -1, T>(v, tw3, t);
+      exchange<R1, C0, N3, SPLIT, T>(v, smem, t);
+      pass_compute<C0, -1, T>(v, tw2, t);
+      exchange<C0, C1, N3, SPLIT, T>(v, smem, t);
+      pass_compute<C1, -1, T>(v, tw2, t);
+      for_outputs<C1>(t, [&](int e, int row, int col) { px[row * N3 + col] = v[e]; });
+    }
   } else {  // PLANE_INV
     const int ob = lid / A.n1, i1 = lid - (lid / A.n1) * A.n1;
     cx<T>* px = reinterpret_cast<cx<T>*>(A.x) + (long long)ob * N + (long long)i1 * PLANE;
@@ -228,8 +290,11 @@ struct PlaneTune {
 };
 constexpr PlaneTune plane_tune(int tbytes, int n2, int n3, int mode) {
   const bool pair = mode == PLANE_PAIR_FWD || mode == PLANE_INV,
-             mac = mode == PLANE_INV_MAC || mode == PLANE_INV_MAC_MIR;
+             mac = mode == PLANE_INV_MAC || mode == PLANE_INV_MAC_MIR || mode == PLANE_DENS;
+  // band loops hold an accumulator or V(r) in registers beside the plane
+  const bool band = mode == PLANE_DENS || mode == PLANE_VMUL;
   if (tbytes == 8) {  // FP64
+    if (band && n2 == 96 && n3 == 128) return PlaneTune{768, true, 1};
     if (n2 == 64 && n3 == 64) return pair ? PlaneTune{512, true, 2} : mac ? PlaneTune{256, false, 2} : PlaneTune{256, true, 1};
     if (n2 == 96 && n3 == 128) return pair ? PlaneTune{512, true, 1} : PlaneTune{1024, true, 1};
     if (n2 == 96 && n3 == 96) return PlaneTune{768, true, 1};
@@ -512,6 +577,49 @@ __global__ void gather_kernel(const cx<T>* __restrict__ box, long long N, const 
   const T st = T(s);
   for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < npw; p += gridDim.x * blockDim.x)
     out[(long long)j * ldo + p] = cscale<T>(box[(long long)j * N + slot[p]], st);
+}
+
+// Band force on the sphere:
+//   out[j][p] = -w[j0+j] * (1/2 |k+G_p|^2 c[j][p] + box[j][slot[p]] / N)
+struct ForceArgs {
+  const void* box;     // [nj][N]: FFT[V psi_j], unnormalised
+  long long N;
+  const int* slot;
+  int npw;
+  const void* c;       // [*][ldc] sphere coefficients (row j0 + j)
+  int ldc;
+  void* out;           // [*][ldo] (row j0 + j)
+  int ldo;
+  const double* w;
+  int j0;
+  double b[3][3];      // reciprocal vectors (rows)
+  double k[3];
+  int n1, n2, n3;
+};
+
+template <typename T>
+__global__ void force_gather_kernel(ForceArgs A) {
+  const int j = blockIdx.y;
+  const double wj = A.w[A.j0 + j];
+  const cx<T>* box = reinterpret_cast<const cx<T>*>(A.box) + (long long)j * A.N;
+  const cx<T>* c = reinterpret_cast<const cx<T>*>(A.c) + (long long)(A.j0 + j) * A.ldc;
+  cx<T>* out = reinterpret_cast<cx<T>*>(A.out) + (long long)(A.j0 + j) * A.ldo;
+  const double inv_n = 1.0 / double(A.N);
+  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < A.npw; p += gridDim.x * blockDim.x) {
+    const int s = A.slot[p];
+    const int i3 = s % A.n3, i12 = s / A.n3;
+    const int i2 = i12 % A.n2, i1 = i12 / A.n2;
+    const int m1 = signed_index(i1, A.n1), m2 = signed_index(i2, A.n2), m3 = signed_index(i3, A.n3);
+    double g2 = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const double ga = A.k[a] + m1 * A.b[0][a] + m2 * A.b[1][a] + m3 * A.b[2][a];
+      g2 += ga * ga;
+    }
+    const cx<T> v = box[s], cp = c[p];
+    const T kin = T(0.5 * g2), sv = T(inv_n), mw = T(-wj);
+    out[p] = mk<T>(mw * (kin * cp.x + sv * v.x), mw * (kin * cp.y + sv * v.y));
+  }
 }
 
 }  // namespace fockx

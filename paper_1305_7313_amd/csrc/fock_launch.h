@@ -23,6 +23,9 @@ template <typename T>
 hipError_t launch_gather(const void* box, long long N, const int* slot, int npw, int nj, void* out, int ldo, double s0,
                          const double* w, int j0, const double* g, hipStream_t s);
 
+template <typename T> hipError_t launch_force_gather(const ForceArgs& a, int nj, hipStream_t s);
+hipError_t launch_group_sum(const double* part, int ngrp, long long N, double* rho, hipStream_t s);
+
 hipError_t launch_energy_tile(const double* epart, int ngroups, const double* f, const double* g, int i0, int j0, int ti,
                               int tj, int sym, double escale, double* tile_e, hipStream_t s);
 hipError_t launch_energy_final(const double* tile_e, int ntiles, double scale, double* ex, hipStream_t s);

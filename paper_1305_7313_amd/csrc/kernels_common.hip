@@ -98,6 +98,24 @@ hipError_t launch_energy_tile(const double* epart, int ngroups, const double* f,
   return hipGetLastError();
 }
 
+// rho[r] = sum_g part[g][r]  (fixed order: bitwise reproducible)
+__global__ void group_sum_kernel(const double* __restrict__ part, int ngrp, long long N, double* __restrict__ rho) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x; r < N; r += stride) {
+    double s = 0.0;
+    for (int g = 0; g < ngrp; ++g) s += part[(long long)g * N + r];
+    rho[r] = s;
+  }
+}
+
+hipError_t launch_group_sum(const double* part, int ngrp, long long N, double* rho, hipStream_t s) {
+  if (N <= 0) return hipSuccess;
+  long long blocks = (N + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(group_sum_kernel, dim3((unsigned)blocks), dim3(256), 0, s, part, ngrp, N, rho);
+  return hipGetLastError();
+}
+
 hipError_t launch_energy_final(const double* tile_e, int ntiles, double scale, double* ex, hipStream_t s) {
   hipLaunchKernelGGL(energy_final_kernel, dim3(1), dim3(64), 0, s, tile_e, ntiles, scale, ex);
   return hipGetLastError();

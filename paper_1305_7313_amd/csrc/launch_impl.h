@@ -19,6 +19,8 @@ hipError_t plane_mode(int mode, const PlaneArgs& a, int nblocks, hipStream_t s) 
     case PLANE_FWD: return plane_go<PLANE_FWD, N2, N3>(a, nblocks, s);
     case PLANE_INV: return plane_go<PLANE_INV, N2, N3>(a, nblocks, s);
     case PLANE_INV_MAC_MIR: return plane_go<PLANE_INV_MAC_MIR, N2, N3>(a, nblocks, s);
+    case PLANE_DENS: return plane_go<PLANE_DENS, N2, N3>(a, nblocks, s);
+    case PLANE_VMUL: return plane_go<PLANE_VMUL, N2, N3>(a, nblocks, s);
   }
   return hipErrorInvalidValue;
 }
@@ -126,6 +128,14 @@ hipError_t launch_gather<FX_T>(const void* box, long long N, const int* slot, in
   const int bx = (npw + 255) / 256;
   hipLaunchKernelGGL(gather_kernel<FX_T>, dim3(bx, nj), dim3(256), 0, s, reinterpret_cast<const cx<FX_T>*>(box), N,
                      slot, npw, reinterpret_cast<cx<FX_T>*>(out), ldo, s0, w, j0, g);
+  return hipGetLastError();
+}
+
+template <>
+hipError_t launch_force_gather<FX_T>(const ForceArgs& a, int nj, hipStream_t s) {
+  if (nj <= 0 || a.npw <= 0) return hipSuccess;
+  const int bx = (a.npw + 255) / 256;
+  hipLaunchKernelGGL(force_gather_kernel<FX_T>, dim3(bx, nj), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

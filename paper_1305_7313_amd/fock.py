@@ -99,6 +99,14 @@ def lib():
         L.fock_fft3d.restype = ctypes.c_int
         L.fock_fft3d.argtypes = [P(ctypes.c_int32), ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
                                  ctypes.c_int32, ctypes.c_void_p]
+        L.fock_band_workspace_size.restype = ctypes.c_size_t
+        L.fock_band_workspace_size.argtypes = [P(fock_cell), ctypes.c_int32, ctypes.c_int32]
+        L.fock_band_density.restype = ctypes.c_int
+        L.fock_band_density.argtypes = [P(fock_cell), ctypes.c_int32, P(fock_orbs), ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_size_t, ctypes.c_void_p]
+        L.fock_band_force.restype = ctypes.c_int
+        L.fock_band_force.argtypes = [P(fock_cell), P(ctypes.c_double), ctypes.c_int32, P(fock_orbs), ctypes.c_void_p,
+                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
         L.fock_exchange_grid.restype = ctypes.c_int
         L.fock_exchange_grid.argtypes = [P(fock_cell), ctypes.c_int32, P(ctypes.c_double), ctypes.c_int32,
                                          P(ctypes.c_int32)]
@@ -188,6 +196,50 @@ def _stream(device=None):
 
 def _qarr(q):
     return (ctypes.c_double * 3)(*[float(x) for x in q])
+
+
+def band_workspace(cell: Cell, dtype: int, nb: int, device):
+    import torch
+    nbytes = int(lib().fock_band_workspace_size(ctypes.byref(cell.c), int(dtype), int(nb)))
+    if nbytes == 0:
+        raise FockError(FOCK_E_UNSUPPORTED_GRID, "fock_band_workspace_size returned 0 for this cell")
+    return torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+
+def fock_band_density(cell: Cell, c, w, out=None, ws=None):
+    """Charge density sum_b w_b |psi_b(r)|^2 on the grid: float64 [n1, n2, n3]
+    (C call: fock_band_density)."""
+    import torch
+    dt = dtype_code(c)
+    if out is None:
+        out = torch.empty(cell.n, dtype=torch.float64, device=c.device)
+    o = orbs(c, w)
+    if ws is None:
+        ws = band_workspace(cell, dt, o.nb, c.device)
+    _check(lib().fock_band_density(ctypes.byref(cell.c), dt, ctypes.byref(o), out.data_ptr(), ws.data_ptr(),
+                                   ws.numel(), _stream(c.device)))
+    return out
+
+
+def fock_band_force(cell: Cell, k, c, w, vloc, out=None, ws=None):
+    """-w_b (1/2 |k+G|^2 c_b + (V psi_b)(G)) on the sphere: [nb, npw] of c's dtype;
+    vloc is real [n1, n2, n3] in c's precision (C call: fock_band_force)."""
+    import torch
+    dt = dtype_code(c)
+    rdt = torch.float64 if dt == FOCK_C128 else torch.float32
+    if vloc.dtype != rdt or not vloc.is_contiguous() or tuple(vloc.shape) != cell.n:
+        raise ValueError("vloc must be a contiguous real [n1, n2, n3] tensor in the orbitals' precision")
+    if out is None:
+        out = torch.empty_like(c)
+    if out.shape != c.shape or out.stride() != c.stride():
+        raise ValueError("out must have the coefficients' shape and strides")
+    o = orbs(c, w)
+    if ws is None:
+        ws = band_workspace(cell, dt, o.nb, c.device)
+    _check(lib().fock_band_force(ctypes.byref(cell.c), _qarr(k), dt, ctypes.byref(o), vloc.data_ptr(),
+                                 out.data_ptr() if out.numel() else None, ws.data_ptr(), ws.numel(),
+                                 _stream(c.device)))
+    return out
 
 
 def fock_exchange_grid(cell: Cell, q=None, dtype: int = FOCK_C128) -> tuple:

@@ -1,4 +1,6 @@
-"""Batched form: several uneven systems in one persistent launch in one hipGraph."""
+"""Batched form: several uneven systems in one hipGraph, either one
+persistent launch over every stage of every system (mode 0) or each system's
+per-shape kernel schedule in turn (mode 1); the tuner keeps the faster."""
 import numpy as np
 import pytest
 
@@ -27,9 +29,12 @@ def _small_batch():
 
 
 @pytest.mark.parametrize("prec", ["c128", "c64"])
-def test_batch_small_vs_single_and_oracle(prec, tmp_path):
+@pytest.mark.parametrize("mode", ["0", "1", "auto"])
+def test_batch_small_vs_single_and_oracle(prec, mode, tmp_path, monkeypatch):
     import torch
     F = _F()
+    if mode != "auto":
+        monkeypatch.setenv("FOCK_BATCH_MODE", mode)
     cdt = torch.complex128 if prec == "c128" else torch.complex64
     tol = 1e-10 if prec == "c128" else 1e-5
     systems = _small_batch()
@@ -38,9 +43,11 @@ def test_batch_small_vs_single_and_oracle(prec, tmp_path):
         cells.append(F.Cell(s.a, s.n, s.miller, g0=gb, gb_alpha=0.6, nq=(2, 2, 2)))
         C.append(torch.from_numpy(c).to(cdt).cuda())
         W.append(torch.from_numpy(f).cuda())
-    print(f"[case] batch small {prec}: create (autotune)", flush=True)
+    print(f"[case] batch small {prec} mode={mode}: create (autotune)", flush=True)
     plan = F.BatchPlan(cells, C, W, tune_cache=str(tmp_path / "tune.json"))
     report(f"batch small {prec} schedule", **{k: v for k, v in plan.info().items()})
+    if mode != "auto":
+        assert plan.info()["mode"] == ("persistent" if mode == "0" else "kernels")
     plan.apply()
     plan.check()
     outs = [host(o).copy() for o in plan.outs]
@@ -70,18 +77,22 @@ def test_batch_small_vs_single_and_oracle(prec, tmp_path):
     plan.check()
     for k in range(len(systems)):
         assert rel_fro(host(plan.outs[k]), 0.5 * outs[k]) < 1e-6
-    # a second plan on the same batch reads the tune cache instead of re-tuning
-    plan2 = F.BatchPlan(cells, C, W, tune_cache=str(tmp_path / "tune.json"))
-    assert {k: plan2.info()[k] for k in ("tile", "units_per_ticket")} == \
-        {k: plan.info()[k] for k in ("tile", "units_per_ticket")}
+    if mode == "auto":
+        # a second plan on the same batch reads the tune cache instead of re-tuning
+        plan2 = F.BatchPlan(cells, C, W, tune_cache=str(tmp_path / "tune.json"))
+        keys = [k for k in ("mode", "tile", "units_per_ticket") if k in plan.info()]
+        assert {k: plan2.info()[k] for k in keys} == {k: plan.info()[k] for k in keys}
+        plan2.close()
     plan.close()
-    plan2.close()
 
 
-def test_batch_config4_fp32():
+@pytest.mark.parametrize("mode", ["0", "1"])
+def test_batch_config4_fp32(mode, monkeypatch):
     """16 systems, grids from {48,64,72,96}^3, 32-242 orbitals, FP32."""
     import torch
     F = _F()
+    monkeypatch.setenv("FOCK_BATCH_MODE", mode)
+    monkeypatch.setenv("FOCK_BATCH_TUNE", "0")
     grids, nbs = synth.config4_layout()
     cells, C, W, sys_ = [], [], [], []
     for k in range(16):
@@ -90,7 +101,7 @@ def test_batch_config4_fp32():
         cells.append(F.Cell(s.a, s.n, s.miller))
         C.append(torch.from_numpy(c).to(torch.complex64).cuda())
         W.append(torch.ones(c.shape[0], dtype=torch.float64, device="cuda"))
-    print("[case] config4 batch create (autotune)", flush=True)
+    print(f"[case] config4 batch create mode={mode}", flush=True)
     plan = F.BatchPlan(cells, C, W)
     report("config4 schedule", **plan.info())
     plan.apply()
