@@ -114,9 +114,16 @@ __device__ __forceinline__ int signed_index(int i, int n) { return i < (n >> 1) 
 // ---------------------------------------------------------------------------
 
 // Plane body: W threads, SPLIT selects the 8-byte (two-round) LDS exchange.
+// Padded LDS tiles (fft_engine.h, Tile) for the planes where they measured
+// faster: FP64 (64^3: -9% per apply) and 128-wide rows.  FP32 planes of
+// other widths keep the compact tile: the padding buys them nothing and on
+// the 96 x 96 plane it costs the second resident workgroup per CU (+15%).
+template <typename T, int N3> constexpr bool plane_tile_pad() { return sizeof(T) == 8 || N3 == 128; }
+
 template <typename T, int N2, int N3, int W, bool SPLIT> struct PlaneGeom {
   static constexpr int PLANE = N2 * N3;
-  static constexpr int XBYTES = Tile<N3>::slots(N2) * (SPLIT ? (int)sizeof(T) : 2 * (int)sizeof(T));
+  static constexpr int XBYTES =
+      Tile<N3, plane_tile_pad<T, N3>()>::slots(N2) * (SPLIT ? (int)sizeof(T) : 2 * (int)sizeof(T));
   using Rw = Axis<N3, N2, true, W>;   // transforms along i3, one per row
   using Cl = Axis<N2, N3, false, W>;  // transforms along i2, one per column
   static constexpr int NV = Rw::NV > Cl::NV ? Rw::NV : Cl::NV;
@@ -131,6 +138,7 @@ __device__ __forceinline__ void plane_body(const PlaneArgs& A, int lid, unsigned
   using C0 = typename Cfg::Cl::P0;
   using C1 = typename Cfg::Cl::P1;
   constexpr int PLANE = Cfg::PLANE;
+  constexpr bool PAD = plane_tile_pad<T, N3>();
   const int t = threadIdx.x;
   const long long N = A.N;
   cx<T> v[Cfg::NV];
@@ -146,11 +154,11 @@ __device__ __forceinline__ void plane_body(const PlaneArgs& A, int lid, unsigned
       v[e] = cmulc<T>(pa[p], pb[p]);
     });
     pass_compute<R0, -1, T>(v, tw3, t);
-    exchange<R0, R1, N3, SPLIT, T>(v, smem, t);
+    exchange<R0, R1, N3, SPLIT, T, PAD>(v, smem, t);
     pass_compute<R1, -1, T>(v, tw3, t);
-    exchange<R1, C0, N3, SPLIT, T>(v, smem, t);
+    exchange<R1, C0, N3, SPLIT, T, PAD>(v, smem, t);
     pass_compute<C0, -1, T>(v, tw2, t);
-    exchange<C0, C1, N3, SPLIT, T>(v, smem, t);
+    exchange<C0, C1, N3, SPLIT, T, PAD>(v, smem, t);
     pass_compute<C1, -1, T>(v, tw2, t);
     cx<T>* pw = reinterpret_cast<cx<T>*>(A.w) + (long long)(ii * A.tj + jj) * N + (long long)i1 * PLANE;
     for_outputs<C1>(t, [&](int e, int row, int col) { pw[row * N3 + col] = v[e]; });
@@ -171,11 +179,11 @@ __device__ __forceinline__ void plane_body(const PlaneArgs& A, int lid, unsigned
       const cx<T>* pw = reinterpret_cast<const cx<T>*>(A.w) + (long long)slot * N + (long long)i1 * PLANE;
       for_inputs<C0>(t, [&](int e, int row, int col) { v[e] = pw[row * N3 + col]; });
       pass_compute<C0, +1, T>(v, tw2, t);
-      exchange<C0, C1, N3, SPLIT, T>(v, smem, t);
+      exchange<C0, C1, N3, SPLIT, T, PAD>(v, smem, t);
       pass_compute<C1, +1, T>(v, tw2, t);
-      exchange<C1, R0, N3, SPLIT, T>(v, smem, t);
+      exchange<C1, R0, N3, SPLIT, T, PAD>(v, smem, t);
       pass_compute<R0, +1, T>(v, tw3, t);
-      exchange<R0, R1, N3, SPLIT, T>(v, smem, t);
+      exchange<R0, R1, N3, SPLIT, T, PAD>(v, smem, t);
       pass_compute<R1, +1, T>(v, tw3, t);
       const T fk = T(A.f[o0 + k] * A.fscale);
       const cx<T>* pa = src + (long long)(o0 + k) * N + (long long)i1 * PLANE;
@@ -205,11 +213,11 @@ __device__ __forceinline__ void plane_body(const PlaneArgs& A, int lid, unsigned
     cx<T>* px = reinterpret_cast<cx<T>*>(A.x) + (long long)ob * N + (long long)i1 * PLANE;
     for_inputs<R0>(t, [&](int e, int row, int col) { v[e] = px[row * N3 + col]; });
     pass_compute<R0, -1, T>(v, tw3, t);
-    exchange<R0, R1, N3, SPLIT, T>(v, smem, t);
+    exchange<R0, R1, N3, SPLIT, T, PAD>(v, smem, t);
     pass_compute<R1, -1, T>(v, tw3, t);
-    exchange<R1, C0, N3, SPLIT, T>(v, smem, t);
+    exchange<R1, C0, N3, SPLIT, T, PAD>(v, smem, t);
     pass_compute<C0, -1, T>(v, tw2, t);
-    exchange<C0, C1, N3, SPLIT, T>(v, smem, t);
+    exchange<C0, C1, N3, SPLIT, T, PAD>(v, smem, t);
     pass_compute<C1, -1, T>(v, tw2, t);
     for_outputs<C1>(t, [&](int e, int row, int col) { px[row * N3 + col] = v[e]; });
   } else if constexpr (MODE == PLANE_DENS) {
@@ -223,11 +231,11 @@ __device__ __forceinline__ void plane_body(const PlaneArgs& A, int lid, unsigned
       const cx<T>* px = reinterpret_cast<const cx<T>*>(A.x) + (long long)b * N + (long long)i1 * PLANE;
       for_inputs<C0>(t, [&](int e, int row, int col) { v[e] = px[row * N3 + col]; });
       pass_compute<C0, +1, T>(v, tw2, t);
-      exchange<C0, C1, N3, SPLIT, T>(v, smem, t);
+      exchange<C0, C1, N3, SPLIT, T, PAD>(v, smem, t);
       pass_compute<C1, +1, T>(v, tw2, t);
-      exchange<C1, R0, N3, SPLIT, T>(v, smem, t);
+      exchange<C1, R0, N3, SPLIT, T, PAD>(v, smem, t);
       pass_compute<R0, +1, T>(v, tw3, t);
-      exchange<R0, R1, N3, SPLIT, T>(v, smem, t);
+      exchange<R0, R1, N3, SPLIT, T, PAD>(v, smem, t);
       pass_compute<R1, +1, T>(v, tw3, t);
       const T wb = T(A.f[A.i0 + b] * A.fscale);
       for_outputs<R1>(t, [&](int e, int row, int col) { acc[e] += wb * (v[e].x * v[e].x + v[e].y * v[e].y); });
@@ -249,20 +257,20 @@ __device__ __forceinline__ void plane_body(const PlaneArgs& A, int lid, unsigned
       cx<T>* px = reinterpret_cast<cx<T>*>(A.x) + (long long)b * N + (long long)i1 * PLANE;
       for_inputs<C0>(t, [&](int e, int row, int col) { v[e] = px[row * N3 + col]; });
       pass_compute<C0, +1, T>(v, tw2, t);
-      exchange<C0, C1, N3, SPLIT, T>(v, smem, t);
+      exchange<C0, C1, N3, SPLIT, T, PAD>(v, smem, t);
       pass_compute<C1, +1, T>(v, tw2, t);
-      exchange<C1, R0, N3, SPLIT, T>(v, smem, t);
+      exchange<C1, R0, N3, SPLIT, T, PAD>(v, smem, t);
       pass_compute<R0, +1, T>(v, tw3, t);
-      exchange<R0, R1, N3, SPLIT, T>(v, smem, t);
+      exchange<R0, R1, N3, SPLIT, T, PAD>(v, smem, t);
       pass_compute<R1, +1, T>(v, tw3, t);
       for_outputs<R1>(t, [&](int e, int row, int col) { v[e] = cscale<T>(v[e], vr[e]); });
-      exchange<R1, R0, N3, SPLIT, T>(v, smem, t);
+      exchange<R1, R0, N3, SPLIT, T, PAD>(v, smem, t);
       pass_compute<R0, -1, T>(v, tw3, t);
-      exchange<R0, R1, N3, SPLIT, T>(v, smem, t);
+      exchange<R0, R1, N3, SPLIT, T, PAD>(v, smem, t);
       pass_compute<R1, -1, T>(v, tw3, t);
-      exchange<R1, C0, N3, SPLIT, T>(v, smem, t);
+      exchange<R1, C0, N3, SPLIT, T, PAD>(v, smem, t);
       pass_compute<C0, -1, T>(v, tw2, t);
-      exchange<C0, C1, N3, SPLIT, T>(v, smem, t);
+      exchange<C0, C1, N3, SPLIT, T, PAD>(v, smem, t);
       pass_compute<C1, -1, T>(v, tw2, t);
       for_outputs<C1>(t, [&](int e, int row, int col) { px[row * N3 + col] = v[e]; });
     }
@@ -271,11 +279,11 @@ __device__ __forceinline__ void plane_body(const PlaneArgs& A, int lid, unsigned
     cx<T>* px = reinterpret_cast<cx<T>*>(A.x) + (long long)ob * N + (long long)i1 * PLANE;
     for_inputs<C0>(t, [&](int e, int row, int col) { v[e] = px[row * N3 + col]; });
     pass_compute<C0, +1, T>(v, tw2, t);
-    exchange<C0, C1, N3, SPLIT, T>(v, smem, t);
+    exchange<C0, C1, N3, SPLIT, T, PAD>(v, smem, t);
     pass_compute<C1, +1, T>(v, tw2, t);
-    exchange<C1, R0, N3, SPLIT, T>(v, smem, t);
+    exchange<C1, R0, N3, SPLIT, T, PAD>(v, smem, t);
     pass_compute<R0, +1, T>(v, tw3, t);
-    exchange<R0, R1, N3, SPLIT, T>(v, smem, t);
+    exchange<R0, R1, N3, SPLIT, T, PAD>(v, smem, t);
     pass_compute<R1, +1, T>(v, tw3, t);
     for_outputs<R1>(t, [&](int e, int row, int col) { px[row * N3 + col] = v[e]; });
   }
