@@ -51,6 +51,8 @@ WORKLOADS = {
                 "the density cutoff) on the coarser exchange grid that keeps the result exact, FP64 (16384 pairs)",
     "c3r_fp32": "the c3_fp32 sphere and orbitals with the Fock cutoff at the wave-function cutoff on the coarser "
                 "exact exchange grid, FP32 (262144 pairs)",
+    "c2g_fp64": "the c2_fp64 cell and sphere with 128 real (Gamma) orbitals applied to themselves, two real "
+                "orbitals per complex transform, FP64 (16384 pairs)",
     "cp_density_fp64": "band loop: charge density sum_b f_b |psi_b(r)|^2 of the 512 c3 orbitals on 96x96x128, FP64",
     "cp_force_fp64": "band loop: force of H = -1/2 nabla^2 + V(r) on the 512 c3 orbitals on 96x96x128 "
                      "(synthetic normal V), FP64",
@@ -166,6 +168,31 @@ def step_bytes(nb, N, bpc, fp64, sym=True):
                 add("p3_plane_inv_mac", ti * tj, ti * tj)
                 add("p3_second", ti * tj + ti + (0 if diag else tj) + tj + (0 if diag else ti),
                     tj + (0 if diag else ti))
+    return acc
+
+
+def gamma_step_bytes(n, N, bpc, ti_max=16, tj_max=8):
+    """Algorithmic bytes per step of the Gamma apply (packed tiles of 16 real
+    occupied x 8 packed targets, only tiles holding a pair i <= j)."""
+    acc = {}
+
+    def add(k, rd, wr):
+        a = acc.setdefault(k, [0.0, 0])
+        a[0] += (rd + wr) * N * bpc
+        a[1] += 1
+
+    m = (n + 1) // 2
+    for j0 in range(0, m, tj_max):
+        tj = min(tj_max, m - j0)
+        for i0 in range(0, n, ti_max):
+            if i0 > 2 * (j0 + tj) - 1:
+                break
+            ti = min(ti_max, n - i0)
+            pi = (ti + 1) // 2  # packed planes holding the tile's occupied orbitals
+            add("p1_pair_plane_fwd", pi + tj, ti * tj)
+            add("p2_pencil_kernel", ti * tj, ti * tj)
+            add("p3_plane_inv_mac", ti * tj + pi + tj, tj)
+            add("p3_second", ti * tj + tj + pi, pi)
     return acc
 
 
@@ -301,6 +328,46 @@ def single_block(name, args, cpu):
         tr = traced(fock, step, args.steps)
         acc = step_bytes(nb, N, bpc, fp64)
         rec["roofline"] = roofline(tr, acc, args.steps, name)
+        rec["kernels"] = {k: {"ms_per_step": round(v[0] / args.steps, 4), "launches_per_step": v[1] / args.steps}
+                          for k, v in tr.items() if v[1]}
+    return rec
+
+
+def gamma_block(name, args, cpu):
+    import torch
+    from paper_1305_7313_amd import fock
+    s, _ = synth.config2(nb=1)
+    c = synth.gamma_orbitals(s.a, s.miller, 128, 0)
+    nb, N = c.shape[0], s.n[0] * s.n[1] * s.n[2]
+    if cpu:
+        cpu = cpu_baseline(s, c)
+    cd = torch.from_numpy(c).cuda()
+    f = torch.ones(nb, dtype=torch.float64, device="cuda")
+    cell = fock.Cell(s.a, s.n, s.miller)
+    out = torch.empty((nb, s.npw), dtype=torch.complex128, device="cuda")
+    ws = torch.empty(int(fock.lib().fock_workspace_size_gamma(fock.ctypes.byref(cell.c), fock.FOCK_C128, nb)),
+                     dtype=torch.uint8, device="cuda")
+
+    def step():
+        fock.fock_apply_gamma(cell, cd, f, out=out, ws=ws)
+
+    dt = run_steps(step, args.steps, args.warmup)
+    # the general path on the same real orbitals, for comparison
+    out2 = torch.empty_like(out)
+    ws2 = fock.workspace(cell, fock.FOCK_C128, nb, nb, cd.device)
+    dt2 = run_steps(lambda: fock.fock_apply(cell, (0.0, 0.0, 0.0), cd, f, cd, out=out2, ws=ws2), args.steps, 1)
+    diff = float(torch.linalg.vector_norm(out - out2) / torch.linalg.vector_norm(out2))
+    pairs = nb * nb
+    rec = {"value": pairs * args.steps / dt, "ms_per_step": 1e3 * dt / args.steps, "dtype": "f64",
+           "config": {"workload": name, "description": WORKLOADS[name], "grid": list(s.n), "npw": s.npw,
+                      "n_occ": nb, "n_tgt": nb, "pairs_per_step": pairs,
+                      "pair_symmetry": "real orbitals packed two per transform and rho_ji = rho_ij reused; pairs "
+                                       "counted as n_occ x n_tgt"},
+           "general_path_ms_per_step": round(1e3 * dt2 / args.steps, 3), "gamma_vs_general_rel": diff,
+           "cpu_baseline": cpu or None}
+    if not args.no_trace:
+        tr = traced(fock, step, args.steps)
+        rec["roofline"] = roofline(tr, gamma_step_bytes(nb, N, 16), args.steps, name)
         rec["kernels"] = {k: {"ms_per_step": round(v[0] / args.steps, 4), "launches_per_step": v[1] / args.steps}
                           for k, v in tr.items() if v[1]}
     return rec
@@ -447,6 +514,8 @@ def main():
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "data": "synthetic"}
     if wl in ("c2_fp64", "c3_fp32", "c3_fp64", "c2r_fp64", "c3r_fp32"):
         r = single_block(wl, args, cpu=not args.no_cpu_baseline)
+    elif wl == "c2g_fp64":
+        r = gamma_block(wl, args, cpu=not args.no_cpu_baseline)
     elif wl.startswith("cp_"):
         r = band_loops(wl, args, cpu=not args.no_cpu_baseline)
     else:

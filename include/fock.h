@@ -92,6 +92,20 @@ size_t fock_workspace_size(const fock_cell *cell, int32_t dtype, int32_t n_occ, 
 fock_status fock_apply(const fock_cell *cell, const double q[3], int32_t dtype, const fock_orbs *occ,
                        const fock_orbs *tgt, void *vx_out, void *ws, size_t ws_bytes, void *stream);
 
+/* Gamma point, real orbitals (section 4 at q = 0, with phi(r) real): V_x of
+ * the block applied to itself, vx_out[j][p] = (V_x psi_j)(G_p) with
+ * occupations orbs.w, as fock_apply(occ = tgt = orbs, q = 0) returns it.
+ * The coefficients must describe real functions: c(-G) = conj(c(G)) on a
+ * sphere that holds -G with every G (otherwise the result is undefined).
+ * Two real orbitals share one complex transform (psi_2q + i psi_2q+1) and,
+ * since K is real and even, each pair transform carries two real pair
+ * densities; with the pair symmetry v_ij = v_ji this needs about a quarter of
+ * the n_occ x n_tgt pair transforms.  vx_out: device [orbs.nb][orbs.ld].
+ * The energy follows as E_x = 1/2 sum_j f_j Re <psi_j | V_x psi_j>. */
+size_t fock_workspace_size_gamma(const fock_cell *cell, int32_t dtype, int32_t nb);
+fock_status fock_apply_gamma(const fock_cell *cell, int32_t dtype, const fock_orbs *orbs, void *vx_out, void *ws,
+                             size_t ws_bytes, void *stream);
+
 /* Exchange energy (section 4, reciprocal-space form):
  * *ex_out = -1/2 sum_ij f_i g_j Omega sum_G K(q+G) |rho_ij(G)|^2, with f = occ.w
  * and g = tgt.w; ex_out is a device FP64 scalar.  Accumulated in FP64 with a

@@ -312,6 +312,26 @@ Layout layout(long long N, int cplx_bytes, int ngroups, int n_occ, int n_tgt) {
   return L;
 }
 
+// Gamma apply: packed orbitals and packed accumulators ([ceil(nb/2)][N] each)
+// and a pair buffer for one packed tile (up to 16 real x 8 packed).
+Layout layout_gamma(long long N, int cplx_bytes, int nb) {
+  const int m = (nb + 1) / 2;
+  const size_t bytes = (size_t)N * cplx_bytes;
+  const int slots = std::max(1, std::min(16, nb) * std::min(8, m));
+  Layout L;
+  size_t off = 0;
+  L.phiA = off; off += align_up(bytes * (size_t)std::max(m, 1));
+  L.phiB = off; off += align_up(bytes * (size_t)std::max(m, 1));
+  L.acc = off;
+  L.w = off; off += align_up(bytes * (size_t)slots);
+  L.epart = off;
+  L.tile_e = off;
+  L.k0 = off; off += align_up(sizeof(double));
+  L.gbpart = off; off += align_up(sizeof(double) * kGbParts);
+  L.total = off;
+  return L;
+}
+
 // k-mesh jobs: every set's real-space orbitals stay resident; one
 // accumulator block; tile partials for every (k <= k') block.
 Layout layout_kmesh(long long N, int cplx_bytes, int ngroups, int nk, int nbmax) {
@@ -439,11 +459,12 @@ struct Engine {
   }
 
   // P1 and P2 of one pair tile (energy: P2 only accumulates partials).
-  fock_status tile_forward(const PlaneArgs& la, const KernelParams& kp, bool energy, double* epart) {
+  fock_status tile_forward(const PlaneArgs& la, const KernelParams& kp, bool energy, double* epart,
+                           int p1_mode = PLANE_PAIR_FWD) {
     const int tt = la.ti * la.tj;
     {
       FX_TRACE(KC_P1);
-      FX_HIP(launch_plane<T>(PLANE_PAIR_FWD, P.n[1], P.n[2], la, tt * P.n[0], s));
+      FX_HIP(launch_plane<T>(p1_mode, P.n[1], P.n[2], la, tt * P.n[0], s));
     }
     PencilArgs pa{};
     pa.x = la.w;
@@ -676,6 +697,62 @@ fock_status apply_impl(const fock_cell* cell, const Plan& P, const double q[3], 
     return E.finish(J.acc_full, tgt->nb, 0, out, tgt->ld, occ->nb > 0 ? s0 : 0.0, wout, gscale);
   }
   return E.pairs(E.kparams(q, q_zero, cell, d_k0), ws, L, J, nullptr);
+}
+
+// Gamma point, real orbitals: V_x applied to the block itself, two real
+// targets packed per complex transform.  Packed tiles: 16 real occupied x 8
+// packed targets (16 real); only tiles that hold a pair i <= j run.
+constexpr int kGammaTi = 16, kGammaTj = 8;
+
+template <typename T>
+fock_status apply_gamma_impl(const fock_cell* cell, const Plan& P, const fock_orbs* o, char* ws, const Layout& L,
+                             hipStream_t s, void* out, double s0) {
+  Engine<T> E(P, s);
+  const int n = o->nb, m = (n + 1) / 2;
+  if (n == 0) return FOCK_OK;
+  const double q0[3] = {0.0, 0.0, 0.0};
+  double* d_k0 = reinterpret_cast<double*>(ws + L.k0);
+  fock_status st = E.g0_constant(cell, true, d_k0, reinterpret_cast<double*>(ws + L.gbpart));
+  if (st != FOCK_OK) return st;
+  void* pk = ws + L.phiA;   // packed orbitals in real space [m][N]
+  void* acc = ws + L.phiB;  // packed accumulators [m][N]
+  const size_t box = (size_t)P.N * sizeof(cx<T>);
+  {
+    FX_TRACE(KC_A1_SCATTER);
+    FX_HIP(launch_zero<T>(pk, P.N * m, s));
+    FX_HIP(launch_scatter_pack<T>(o->c, o->ld, P.d_slot, P.npw, n, pk, P.N, s));
+  }
+  if ((st = E.transform(pk, m, +1)) != FOCK_OK) return st;
+  {
+    FX_TRACE_S(KC_ZERO);
+    FX_HIP(launch_zero<T>(acc, P.N * m, s));
+  }
+  const KernelParams kp = E.kparams(q0, true, cell, d_k0);
+  for (int j0 = 0; j0 < m; j0 += kGammaTj) {
+    const int tj = std::min(kGammaTj, m - j0);
+    for (int i0 = 0; i0 < n && i0 <= 2 * (j0 + tj) - 1; i0 += kGammaTi) {
+      const int ti = std::min(kGammaTi, n - i0);
+      PlaneArgs la = E.plane_args(pk, pk, ws + L.w, nullptr, o->w, i0, j0, ti, tj);
+      la.nreal = n;
+      if ((st = E.tile_forward(la, kp, false, nullptr, PLANE_PAIR_FWD_G)) != FOCK_OK) return st;
+      PlaneArgs lp = la;
+      lp.acc = static_cast<char*>(acc) + (size_t)j0 * box;
+      {
+        FX_TRACE(KC_P3);
+        FX_HIP(launch_plane<T>(PLANE_INV_MAC_G, P.n[1], P.n[2], lp, tj * P.n[0], s));
+      }
+      PlaneArgs lb = la;
+      lb.acc = static_cast<char*>(acc) + (size_t)(i0 / 2) * box;
+      {
+        FX_TRACE(KC_P3B);
+        FX_HIP(launch_plane<T>(PLANE_INV_MAC_MIR_G, P.n[1], P.n[2], lb, ti * P.n[0], s));
+      }
+    }
+  }
+  if ((st = E.transform(acc, m, -1)) != FOCK_OK) return st;
+  FX_TRACE(KC_A7_GATHER);
+  FX_HIP(launch_gather_unpack<T>(acc, P.N, P.d_slot, P.npw, P.n, n, out, o->ld, s0, s));
+  return FOCK_OK;
 }
 
 template <typename T>
@@ -1581,6 +1658,39 @@ fock_status fock_apply(const fock_cell* cell, const double q[3], int32_t dtype, 
   if (dtype == FOCK_C128)
     return apply_impl<double>(cell, P, q, pr.q_zero, occ, tgt, w, pr.L, s, vx_out, s0, nullptr, nullptr);
   return apply_impl<float>(cell, P, q, pr.q_zero, occ, tgt, w, pr.L, s, vx_out, s0, nullptr, nullptr);
+}
+
+size_t fock_workspace_size_gamma(const fock_cell* cell, int32_t dtype, int32_t nb) {
+  if (!cell || nb < 0 || (dtype != FOCK_C128 && dtype != FOCK_C64)) return 0;
+  if (!grid_supported(cell->n, dtype)) return 0;
+  const long long N = (long long)cell->n[0] * cell->n[1] * cell->n[2];
+  return layout_gamma(N, dtype == FOCK_C128 ? 16 : 8, nb).total;
+}
+
+fock_status fock_apply_gamma(const fock_cell* cell, int32_t dtype, const fock_orbs* orbs, void* vx_out, void* ws,
+                             size_t ws_bytes, void* stream) {
+  fock_status st = check_cell_host(cell, dtype);
+  if (st != FOCK_OK) return st;
+  if (!grid_supported(cell->n, dtype))
+    return fail(FOCK_E_UNSUPPORTED_GRID, "no compiled transforms for grid " + grid_str(cell->n));
+  if ((st = check_orbs(orbs, cell->npw, "orbs")) != FOCK_OK) return st;
+  const double q0[3] = {0.0, 0.0, 0.0};
+  if ((st = check_alias(cell, q0, 1)) != FOCK_OK) return st;
+  if (orbs->nb > 0 && !vx_out) return fail(FOCK_E_ARG, "vx_out is NULL");
+  const long long N = (long long)cell->n[0] * cell->n[1] * cell->n[2];
+  const Layout L = layout_gamma(N, dtype == FOCK_C128 ? 16 : 8, orbs->nb);
+  if (!ws || ws_bytes < L.total) {
+    char buf[160];
+    std::snprintf(buf, sizeof buf, "workspace of %zu bytes is smaller than the %zu needed", ws_bytes, L.total);
+    return fail(FOCK_E_WORKSPACE, buf);
+  }
+  std::shared_ptr<Plan> P;
+  if ((st = get_plan(cell, dtype, &P)) != FOCK_OK) return st;
+  const double s0 = -1.0 / (P->omega * (double)P->N * (double)P->N);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  char* w = static_cast<char*>(ws);
+  if (dtype == FOCK_C128) return apply_gamma_impl<double>(cell, *P, orbs, w, L, s, vx_out, s0);
+  return apply_gamma_impl<float>(cell, *P, orbs, w, L, s, vx_out, s0);
 }
 
 fock_status fock_energy(const fock_cell* cell, const double q[3], int32_t dtype, const fock_orbs* occ,

@@ -32,6 +32,10 @@ enum PlaneMode : int {
   PLANE_INV_MAC_MIR = 4,  // P3, mirrored half of the pair-symmetric schedule
   PLANE_DENS = 5,      // band loop: backward plane FFT, accumulate w |psi|^2
   PLANE_VMUL = 6,      // band loop, in place: backward plane FFT, x V(r), forward plane FFT
+  // Gamma point, real orbitals packed two per complex array (P_q = psi_2q + i psi_2q+1)
+  PLANE_PAIR_FWD_G = 7,    // P1: phi_i(r) P_q(r), forward plane FFT
+  PLANE_INV_MAC_G = 8,     // P3 into the packed targets' accumulators
+  PLANE_INV_MAC_MIR_G = 9, // P3 mirror into the occupied orbitals' accumulator components
 };
 enum PencilMode : int {
   PENCIL_FKI = 0,  // P2: forward, kernel, backward (+ optional energy partials)
@@ -69,6 +73,7 @@ struct PlaneArgs {
   double* part;        // PLANE_DENS: FP64 partial densities [ngrp][N]
   int accumulate;      // PLANE_DENS: add to part (else overwrite)
   const void* vloc;    // PLANE_VMUL: real potential V(r) [N], path precision
+  int nreal;           // Gamma modes: number of real orbitals (packed arrays hold ceil(nreal / 2))
 };
 
 struct PencilArgs {
@@ -143,16 +148,28 @@ __device__ __forceinline__ void plane_body(const PlaneArgs& A, int lid, unsigned
   const long long N = A.N;
   cx<T> v[Cfg::NV];
 
-  if constexpr (MODE == PLANE_PAIR_FWD) {
+  if constexpr (MODE == PLANE_PAIR_FWD || MODE == PLANE_PAIR_FWD_G) {
     const int tt = A.ti * A.tj;
     const int i1 = lid / tt, rem = lid - i1 * tt;
     const int ii = rem / A.tj, jj = rem - ii * A.tj;
-    const cx<T>* pa = reinterpret_cast<const cx<T>*>(A.a) + (long long)(A.i0 + ii) * N + (long long)i1 * PLANE;
     const cx<T>* pb = reinterpret_cast<const cx<T>*>(A.bsrc) + (long long)(A.j0 + jj) * N + (long long)i1 * PLANE;
-    for_inputs<R0>(t, [&](int e, int row, int col) {
-      const int p = row * N3 + col;
-      v[e] = cmulc<T>(pa[p], pb[p]);
-    });
+    if constexpr (MODE == PLANE_PAIR_FWD) {
+      const cx<T>* pa = reinterpret_cast<const cx<T>*>(A.a) + (long long)(A.i0 + ii) * N + (long long)i1 * PLANE;
+      for_inputs<R0>(t, [&](int e, int row, int col) {
+        const int p = row * N3 + col;
+        v[e] = cmulc<T>(pa[p], pb[p]);
+      });
+    } else {
+      // real phi_i is one component of the packed occupied array
+      const int i = A.i0 + ii;
+      const cx<T>* pa = reinterpret_cast<const cx<T>*>(A.a) + (long long)(i >> 1) * N + (long long)i1 * PLANE;
+      const bool hi = i & 1;
+      for_inputs<R0>(t, [&](int e, int row, int col) {
+        const int p = row * N3 + col;
+        const cx<T> a = pa[p];
+        v[e] = cscale<T>(pb[p], hi ? a.y : a.x);
+      });
+    }
     pass_compute<R0, -1, T>(v, tw3, t);
     exchange<R0, R1, N3, SPLIT, T, PAD>(v, smem, t);
     pass_compute<R1, -1, T>(v, tw3, t);
@@ -208,6 +225,68 @@ __device__ __forceinline__ void plane_body(const PlaneArgs& A, int lid, unsigned
       const int p = row * N3 + col;
       pc[p] = cadd<T>(pc[p], s[e]);
     });
+  } else if constexpr (MODE == PLANE_INV_MAC_G || MODE == PLANE_INV_MAC_MIR_G) {
+    // Gamma tiles: real occupied i = i0 + ii, packed targets q = j0 + jj with
+    // v = v_{i,2q} + i v_{i,2q+1}.  Each unordered pair counts once per
+    // accumulator: a pair (i, j) adds f_i phi_i v_ij to acc_j when i <= j and
+    // f_j phi_j v_ij to acc_i when i < j (the weights below vanish otherwise,
+    // which only happens on the diagonal tiles).
+    // PLANE_INV_MAC_G: block (jj, i1), loop over ii, into packed acc_q.
+    // PLANE_INV_MAC_MIR_G: block (ii, i1), loop over jj, into component
+    // (i & 1) of packed acc_{i/2} (acc points at the tile's first pair).
+    constexpr bool mir = MODE == PLANE_INV_MAC_MIR_G;
+    const int nblk = mir ? A.ti : A.tj, nloop = mir ? A.tj : A.ti;
+    const int i1 = lid / nblk, bi = lid - (lid / nblk) * nblk;
+    cx<T> s[R1::NV];
+#pragma unroll
+    for (int e = 0; e < R1::NV; ++e) s[e] = mk<T>(T(0), T(0));
+    for (int k = 0; k < nloop; ++k) {
+      const int ii = mir ? bi : k, jj = mir ? k : bi;
+      const int i = A.i0 + ii, q = A.j0 + jj;
+      const int j0r = 2 * q, j1r = 2 * q + 1;
+      const cx<T>* pw = reinterpret_cast<const cx<T>*>(A.w) + (long long)(ii * A.tj + jj) * N + (long long)i1 * PLANE;
+      for_inputs<C0>(t, [&](int e, int row, int col) { v[e] = pw[row * N3 + col]; });
+      pass_compute<C0, +1, T>(v, tw2, t);
+      exchange<C0, C1, N3, SPLIT, T, PAD>(v, smem, t);
+      pass_compute<C1, +1, T>(v, tw2, t);
+      exchange<C1, R0, N3, SPLIT, T, PAD>(v, smem, t);
+      pass_compute<R0, +1, T>(v, tw3, t);
+      exchange<R0, R1, N3, SPLIT, T, PAD>(v, smem, t);
+      pass_compute<R1, +1, T>(v, tw3, t);
+      if constexpr (mir) {
+        const T m0 = i < j0r ? T(A.f[j0r] * A.fscale) : T(0);
+        const T m1 = (i < j1r && j1r < A.nreal) ? T(A.f[j1r] * A.fscale) : T(0);
+        const cx<T>* pq = reinterpret_cast<const cx<T>*>(A.bsrc) + (long long)q * N + (long long)i1 * PLANE;
+        for_outputs<R1>(t, [&](int e, int row, int col) {
+          const cx<T> pp = pq[row * N3 + col];
+          s[e].x += m0 * pp.x * v[e].x + m1 * pp.y * v[e].y;
+        });
+      } else {
+        const T w0 = i <= j0r ? T(A.f[i] * A.fscale) : T(0);
+        const T w1 = (i <= j1r && j1r < A.nreal) ? T(A.f[i] * A.fscale) : T(0);
+        const cx<T>* pa = reinterpret_cast<const cx<T>*>(A.a) + (long long)(i >> 1) * N + (long long)i1 * PLANE;
+        const bool hi = i & 1;
+        for_outputs<R1>(t, [&](int e, int row, int col) {
+          const cx<T> a = pa[row * N3 + col];
+          const T ph = hi ? a.y : a.x;
+          s[e] = mk<T>(s[e].x + w0 * ph * v[e].x, s[e].y + w1 * ph * v[e].y);
+        });
+      }
+    }
+    if constexpr (mir) {
+      T* pc = reinterpret_cast<T*>(reinterpret_cast<cx<T>*>(A.acc) + (long long)(bi >> 1) * N + (long long)i1 * PLANE) +
+              (bi & 1);
+      for_outputs<R1>(t, [&](int e, int row, int col) {
+        const int p = 2 * (row * N3 + col);
+        pc[p] += s[e].x;
+      });
+    } else {
+      cx<T>* pc = reinterpret_cast<cx<T>*>(A.acc) + (long long)bi * N + (long long)i1 * PLANE;
+      for_outputs<R1>(t, [&](int e, int row, int col) {
+        const int p = row * N3 + col;
+        pc[p] = cadd<T>(pc[p], s[e]);
+      });
+    }
   } else if constexpr (MODE == PLANE_FWD) {
     const int ob = lid / A.n1, i1 = lid - (lid / A.n1) * A.n1;
     cx<T>* px = reinterpret_cast<cx<T>*>(A.x) + (long long)ob * N + (long long)i1 * PLANE;
@@ -297,8 +376,9 @@ struct PlaneTune {
   int minb;
 };
 constexpr PlaneTune plane_tune(int tbytes, int n2, int n3, int mode) {
-  const bool pair = mode == PLANE_PAIR_FWD || mode == PLANE_INV,
-             mac = mode == PLANE_INV_MAC || mode == PLANE_INV_MAC_MIR || mode == PLANE_DENS;
+  const bool pair = mode == PLANE_PAIR_FWD || mode == PLANE_INV || mode == PLANE_PAIR_FWD_G,
+             mac = mode == PLANE_INV_MAC || mode == PLANE_INV_MAC_MIR || mode == PLANE_DENS ||
+                   mode == PLANE_INV_MAC_G || mode == PLANE_INV_MAC_MIR_G;
   // band loops hold an accumulator or V(r) in registers beside the plane
   const bool band = mode == PLANE_DENS || mode == PLANE_VMUL;
   if (tbytes == 8) {  // FP64
@@ -585,6 +665,47 @@ __global__ void gather_kernel(const cx<T>* __restrict__ box, long long N, const 
   const T st = T(s);
   for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < npw; p += gridDim.x * blockDim.x)
     out[(long long)j * ldo + p] = cscale<T>(box[(long long)j * N + slot[p]], st);
+}
+
+// Gamma packing of real orbitals: box[q][slot[p]] = c[2q][p] + i c[2q+1][p]
+// (the second row is absent for the last q of an odd count).
+template <typename T>
+__global__ void scatter_pack_kernel(const cx<T>* __restrict__ c, int ldc, const int* __restrict__ slot, int npw,
+                                    int nreal, cx<T>* __restrict__ box, long long N) {
+  const int q = blockIdx.y;
+  const bool two = 2 * q + 1 < nreal;
+  const cx<T>* c0 = c + (long long)(2 * q) * ldc;
+  const cx<T>* c1 = c0 + ldc;
+  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < npw; p += gridDim.x * blockDim.x) {
+    const cx<T> a = c0[p];
+    const cx<T> b = two ? c1[p] : mk<T>(T(0), T(0));
+    box[(long long)q * N + slot[p]] = mk<T>(a.x - b.y, a.y + b.x);
+  }
+}
+
+// Unpack the transform F = FFT[acc_2q + i acc_2q+1] of two real functions on
+// the sphere: FFT[acc_2q](G) = (F(G) + conj F(-G)) / 2 and
+// FFT[acc_2q+1](G) = (F(G) - conj F(-G)) / (2i); rows 2q and 2q+1 of out,
+// scaled by s0.
+template <typename T>
+__global__ void gather_unpack_kernel(const cx<T>* __restrict__ box, long long N, const int* __restrict__ slot,
+                                     int npw, int n1, int n2, int n3, int nreal, cx<T>* __restrict__ out, int ldo,
+                                     double s0) {
+  const int q = blockIdx.y;
+  const bool two = 2 * q + 1 < nreal;
+  const cx<T>* F = box + (long long)q * N;
+  cx<T>* o0 = out + (long long)(2 * q) * ldo;
+  cx<T>* o1 = o0 + ldo;
+  const T h = T(0.5 * s0);
+  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < npw; p += gridDim.x * blockDim.x) {
+    const int s = slot[p];
+    const int i3 = s % n3, i12 = s / n3;
+    const int i2 = i12 % n2, i1 = i12 / n2;
+    const int sm = (((n1 - i1) % n1) * n2 + (n2 - i2) % n2) * n3 + (n3 - i3) % n3;
+    const cx<T> f = F[s], g = F[sm];
+    o0[p] = mk<T>(h * (f.x + g.x), h * (f.y - g.y));
+    if (two) o1[p] = mk<T>(h * (f.y + g.y), h * (g.x - f.x));
+  }
 }
 
 // Band force on the sphere:

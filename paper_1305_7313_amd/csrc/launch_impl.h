@@ -21,6 +21,9 @@ hipError_t plane_mode(int mode, const PlaneArgs& a, int nblocks, hipStream_t s) 
     case PLANE_INV_MAC_MIR: return plane_go<PLANE_INV_MAC_MIR, N2, N3>(a, nblocks, s);
     case PLANE_DENS: return plane_go<PLANE_DENS, N2, N3>(a, nblocks, s);
     case PLANE_VMUL: return plane_go<PLANE_VMUL, N2, N3>(a, nblocks, s);
+    case PLANE_PAIR_FWD_G: return plane_go<PLANE_PAIR_FWD_G, N2, N3>(a, nblocks, s);
+    case PLANE_INV_MAC_G: return plane_go<PLANE_INV_MAC_G, N2, N3>(a, nblocks, s);
+    case PLANE_INV_MAC_MIR_G: return plane_go<PLANE_INV_MAC_MIR_G, N2, N3>(a, nblocks, s);
   }
   return hipErrorInvalidValue;
 }
@@ -128,6 +131,27 @@ hipError_t launch_gather<FX_T>(const void* box, long long N, const int* slot, in
   const int bx = (npw + 255) / 256;
   hipLaunchKernelGGL(gather_kernel<FX_T>, dim3(bx, nj), dim3(256), 0, s, reinterpret_cast<const cx<FX_T>*>(box), N,
                      slot, npw, reinterpret_cast<cx<FX_T>*>(out), ldo, s0, w, j0, g);
+  return hipGetLastError();
+}
+
+template <>
+hipError_t launch_scatter_pack<FX_T>(const void* c, int ldc, const int* slot, int npw, int nreal, void* box,
+                                     long long N, hipStream_t s) {
+  const int m = (nreal + 1) / 2;
+  if (m <= 0 || npw <= 0) return hipSuccess;
+  hipLaunchKernelGGL(scatter_pack_kernel<FX_T>, dim3((npw + 255) / 256, m), dim3(256), 0, s,
+                     reinterpret_cast<const cx<FX_T>*>(c), ldc, slot, npw, nreal, reinterpret_cast<cx<FX_T>*>(box), N);
+  return hipGetLastError();
+}
+
+template <>
+hipError_t launch_gather_unpack<FX_T>(const void* box, long long N, const int* slot, int npw, const int n[3],
+                                      int nreal, void* out, int ldo, double s0, hipStream_t s) {
+  const int m = (nreal + 1) / 2;
+  if (m <= 0 || npw <= 0) return hipSuccess;
+  hipLaunchKernelGGL(gather_unpack_kernel<FX_T>, dim3((npw + 255) / 256, m), dim3(256), 0, s,
+                     reinterpret_cast<const cx<FX_T>*>(box), N, slot, npw, n[0], n[1], n[2], nreal,
+                     reinterpret_cast<cx<FX_T>*>(out), ldo, s0);
   return hipGetLastError();
 }
 

@@ -107,6 +107,11 @@ def lib():
         L.fock_band_force.restype = ctypes.c_int
         L.fock_band_force.argtypes = [P(fock_cell), P(ctypes.c_double), ctypes.c_int32, P(fock_orbs), ctypes.c_void_p,
                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
+        L.fock_workspace_size_gamma.restype = ctypes.c_size_t
+        L.fock_workspace_size_gamma.argtypes = [P(fock_cell), ctypes.c_int32, ctypes.c_int32]
+        L.fock_apply_gamma.restype = ctypes.c_int
+        L.fock_apply_gamma.argtypes = [P(fock_cell), ctypes.c_int32, P(fock_orbs), ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.c_size_t, ctypes.c_void_p]
         L.fock_exchange_grid.restype = ctypes.c_int
         L.fock_exchange_grid.argtypes = [P(fock_cell), ctypes.c_int32, P(ctypes.c_double), ctypes.c_int32,
                                          P(ctypes.c_int32)]
@@ -196,6 +201,26 @@ def _stream(device=None):
 
 def _qarr(q):
     return (ctypes.c_double * 3)(*[float(x) for x in q])
+
+
+def fock_apply_gamma(cell: Cell, c, f, out=None, ws=None):
+    """V_x of a block of real (Gamma) orbitals applied to itself: [nb, npw]
+    (C call: fock_apply_gamma; c must hold c(-G) = conj(c(G)))."""
+    import torch
+    dt = dtype_code(c)
+    if out is None:
+        out = torch.empty((c.shape[0], cell.npw), dtype=c.dtype, device=c.device)
+    o = orbs(c, f)
+    if out.shape[0] > 1 and out.stride(0) != o.ld:
+        raise ValueError("out must have the orbitals' leading dimension")
+    if ws is None:
+        nbytes = int(lib().fock_workspace_size_gamma(ctypes.byref(cell.c), dt, o.nb))
+        if nbytes == 0:
+            raise FockError(FOCK_E_UNSUPPORTED_GRID, "fock_workspace_size_gamma returned 0 for this cell")
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=c.device)
+    _check(lib().fock_apply_gamma(ctypes.byref(cell.c), dt, ctypes.byref(o), out.data_ptr() if out.numel() else None,
+                                  ws.data_ptr(), ws.numel(), _stream(c.device)))
+    return out
 
 
 def band_workspace(cell: Cell, dtype: int, nb: int, device):

@@ -89,6 +89,30 @@ def random_orbitals(a: np.ndarray, miller: np.ndarray, nb: int, seed: int) -> np
     return np.ascontiguousarray(loewdin(c))
 
 
+def gamma_orbitals(a: np.ndarray, miller: np.ndarray, nb: int, seed: int) -> np.ndarray:
+    """[nb, npw] orthonormal coefficients of real orbitals (Gamma point):
+    c(-G) = conj(c(G)).  The draws of random_orbitals are made Hermitian,
+    (c(G) + conj(c(-G))) / 2, then Loewdin-orthonormalised with the (real)
+    overlap of real functions, which keeps them Hermitian.  The sphere must
+    hold -G with every G."""
+    m = np.asarray(miller)
+    index = {tuple(v): p for p, v in enumerate(m)}
+    neg = np.array([index[tuple(-v)] for v in m])
+    rng = np.random.default_rng(seed)
+    npw = m.shape[0]
+    if nb > npw:
+        raise ValueError("more orbitals than plane waves")
+    c = rng.standard_normal((nb, npw)) + 1j * rng.standard_normal((nb, npw))
+    c = 0.5 * (c + np.conj(c[:, neg]))
+    c *= 1.0 / (1.0 + sphere_g2(a, miller)) ** 2
+    if nb == 0:
+        return c
+    s = (np.conj(c) @ c.T).real
+    w, v = np.linalg.eigh(s)
+    s_mhalf = (v * (1.0 / np.sqrt(w))) @ v.T
+    return np.ascontiguousarray(s_mhalf.T @ c)
+
+
 @dataclasses.dataclass
 class System:
     """One cell with its grid, sphere and orbital blocks."""

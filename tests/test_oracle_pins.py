@@ -312,3 +312,19 @@ def test_kmesh_gradient_finite_difference():
     fd = (ep - em) / (2 * h)
     an = 2.0 * sum(np.sum(np.conj(g) * x).real for g, x in zip(grads, d))
     assert abs(fd - an) < 1e-8 * abs(an)
+
+
+def test_gamma_real_orbitals_give_a_real_exchange_potential():
+    """For real orbitals at q = 0 every pair density and potential is real, so
+    V_x psi is a real function: its coefficients are Hermitian."""
+    s = synth.make_system(synth.cubic_cell(8.0), (24, 24, 24))
+    c = synth.gamma_orbitals(s.a, s.miller, 5, 6)
+    f = np.array([1.0, 0.9, 0.6, 0.4, 0.2])
+    v = exx.fock_apply(s.a, s.n, s.miller, np.zeros(3), c, f, c)
+    index = {tuple(m): p for p, m in enumerate(s.miller)}
+    neg = np.array([index[tuple(-m)] for m in s.miller])
+    assert np.abs(v - np.conj(v[:, neg])).max() < 1e-14 * np.abs(v).max()
+    # and not trivially: a complex block breaks the symmetry
+    cz = synth.random_orbitals(s.a, s.miller, 5, 6)
+    vz = exx.fock_apply(s.a, s.n, s.miller, np.zeros(3), cz, f, cz)
+    assert np.abs(vz - np.conj(vz[:, neg])).max() > 1e-3 * np.abs(vz).max()

@@ -27,3 +27,12 @@ def test_sphere_is_alias_free():
         s = synth.make_system(np.diag([n[0] / 3.2, n[1] / 3.0, n[2] / 2.9]), n)
         for ax in range(3):
             assert np.abs(s.miller[:, ax]).max() <= (n[ax] - 1) / 4
+
+
+def test_gamma_orbitals_are_real_and_orthonormal():
+    from oracle import exx
+    s = synth.make_system(synth.cubic_cell(8.0), (24, 24, 24))
+    c = synth.gamma_orbitals(s.a, s.miller, 6, 4)
+    assert np.abs(np.conj(c) @ c.T - np.eye(6)).max() < 1e-13
+    psi = exx.to_grid(c, s.miller, s.n)
+    assert np.abs(psi.imag).max() < 1e-13 * np.abs(psi.real).max()
