@@ -368,22 +368,29 @@ __device__ __forceinline__ void plane_body(const PlaneArgs& A, int lid, unsigned
   }
 }
 
-// Default block shape per precision, plane and mode (measured on MI355X:
-// block size, LDS exchange width and occupancy hint of the fastest variant).
+// Default block shape per precision, plane and mode (measured on MI355X with
+// a sweep of every valid block size, LDS exchange width and occupancy hint
+// per plane kernel on 16 x 16 pair tiles; the fastest variant is kept).
 struct PlaneTune {
   int w;
   bool split;
   int minb;
 };
 constexpr PlaneTune plane_tune(int tbytes, int n2, int n3, int mode) {
-  const bool pair = mode == PLANE_PAIR_FWD || mode == PLANE_INV || mode == PLANE_PAIR_FWD_G,
-             mac = mode == PLANE_INV_MAC || mode == PLANE_INV_MAC_MIR || mode == PLANE_DENS ||
-                   mode == PLANE_INV_MAC_G || mode == PLANE_INV_MAC_MIR_G;
+  const bool p1 = mode == PLANE_PAIR_FWD || mode == PLANE_PAIR_FWD_G, inv = mode == PLANE_INV,
+             pair = p1 || inv,
+             fwdmac = mode == PLANE_INV_MAC || mode == PLANE_INV_MAC_G,
+             mirror = mode == PLANE_INV_MAC_MIR || mode == PLANE_INV_MAC_MIR_G,
+             mac = fwdmac || mirror || mode == PLANE_DENS;
   // band loops hold an accumulator or V(r) in registers beside the plane
   const bool band = mode == PLANE_DENS || mode == PLANE_VMUL;
   if (tbytes == 8) {  // FP64
     if (band && n2 == 96 && n3 == 128) return PlaneTune{768, true, 1};
-    if (n2 == 64 && n3 == 64) return pair ? PlaneTune{512, true, 2} : mac ? PlaneTune{256, false, 2} : PlaneTune{256, true, 1};
+    if (n2 == 64 && n3 == 64) {
+      if (pair) return PlaneTune{512, true, 2};
+      if (mirror) return PlaneTune{512, false, 1};
+      return mac ? PlaneTune{256, false, 2} : PlaneTune{256, true, 1};
+    }
     if (n2 == 96 && n3 == 128) return pair ? PlaneTune{512, true, 1} : PlaneTune{1024, true, 1};
     if (n2 == 96 && n3 == 96) return PlaneTune{768, true, 1};
     if (n2 == 72 && n3 == 72) return PlaneTune{576, true, 1};
@@ -391,12 +398,12 @@ constexpr PlaneTune plane_tune(int tbytes, int n2, int n3, int mode) {
     if (n2 == 48 && n3 == 48) return PlaneTune{384, false, 1};
     return PlaneTune{192, false, 1};
   }
-  if (n2 == 96 && n3 == 128) return pair ? PlaneTune{512, true, 1} : PlaneTune{1024, false, 1};
-  if (n2 == 96 && n3 == 96) return mac ? PlaneTune{384, false, 1} : PlaneTune{768, false, 1};
-  if (n2 == 72 && n3 == 72) return PlaneTune{576, false, 1};
+  if (n2 == 96 && n3 == 128) return p1 ? PlaneTune{512, true, 2} : inv ? PlaneTune{512, true, 1} : PlaneTune{1024, false, 1};
+  if (n2 == 96 && n3 == 96) return mac ? PlaneTune{384, false, 1} : inv ? PlaneTune{768, true, 1} : PlaneTune{768, false, 1};
+  if (n2 == 72 && n3 == 72) return p1 ? PlaneTune{720, false, 1} : inv ? PlaneTune{720, true, 2} : PlaneTune{576, false, 1};
   if (n2 == 64 && n3 == 64) return PlaneTune{512, false, 1};
   if (n2 == 48 && n3 == 64) return PlaneTune{256, false, 1};
-  if (n2 == 48 && n3 == 48) return pair ? PlaneTune{192, false, 1} : PlaneTune{384, false, 1};
+  if (n2 == 48 && n3 == 48) return p1 ? PlaneTune{192, false, 1} : PlaneTune{384, false, 1};
   return PlaneTune{192, false, 1};
 }
 
