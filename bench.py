@@ -53,6 +53,10 @@ WORKLOADS = {
                 "exact exchange grid, FP32 (262144 pairs)",
     "c2g_fp64": "the c2_fp64 cell and sphere with 128 real (Gamma) orbitals applied to themselves, two real "
                 "orbitals per complex transform, FP64 (16384 pairs)",
+    "c5_fp32_grad": "72^3 cubic L=24, 2x2x2 k-mesh, 256 orbitals per k, GB G=0 term: E_x and its gradient "
+                    "(one forward and one backward), FP32 (4194304 pairs in E_x)",
+    "c5r_fp32_grad": "the c5_fp32_grad mesh and orbitals with the Fock cutoff at the wave-function cutoff on the "
+                     "coarser exact exchange grid for every q = k - k', FP32 (4194304 pairs in E_x)",
     "cp_density_fp64": "band loop: charge density sum_b f_b |psi_b(r)|^2 of the 512 c3 orbitals on 96x96x128, FP64",
     "cp_force_fp64": "band loop: force of H = -1/2 nabla^2 + V(r) on the 512 c3 orbitals on 96x96x128 "
                      "(synthetic normal V), FP64",
@@ -373,6 +377,55 @@ def gamma_block(name, args, cpu):
     return rec
 
 
+# Algorithmic bytes per launch of each class on full 16 x 16 tiles (units of N*b).
+TILE_BYTES = {"p1_pair_plane_fwd": 16 + 16 + 256, "p2_pencil_energy": 256, "p2_pencil_kernel": 512,
+              "p3_plane_inv_mac": 256 + 16 + 32, "p3_second": 256 + 16 + 32}
+
+
+def kmesh_grad(name, args, cpu):
+    import torch
+    from paper_1305_7313_amd import fock
+    s, kpts, orbs = synth.config5()
+    nk, nb = len(orbs), orbs[0].shape[0]
+    N = s.n[0] * s.n[1] * s.n[2]
+    if cpu:
+        cpu = cpu_baseline(s, orbs[0])
+    n, ecut = tuple(s.n), 0.0
+    if name.startswith("c5r"):
+        ecut = s.ecut
+        qs = [ki - kj for ki in kpts for kj in kpts]
+        n = fock.fock_exchange_grid(fock.Cell(s.a, s.n, s.miller, ecut_fock=ecut), qs, dtype=fock.FOCK_C64)
+        N = n[0] * n[1] * n[2]
+    cell = fock.Cell(s.a, n, s.miller, ecut_fock=ecut, g0=fock.FOCK_G0_GB, gb_alpha=10.0 / s.ecut, nq=(2, 2, 2))
+    C = torch.from_numpy(np.stack(orbs)).to(torch.complex64).cuda()
+    W = torch.full((nk, nb), 1.0 / nk, dtype=torch.float64, device="cuda")
+    ws = fock.workspace_kmesh(cell, fock.FOCK_C64, nk, nb, C.device)
+    ex = torch.empty((), dtype=torch.float64, device="cuda")
+    one = torch.ones((), dtype=torch.float64, device="cuda")
+    G = torch.empty_like(C)
+
+    def step():
+        fock.fock_energy_kmesh(cell, kpts, C, W, out=ex, ws=ws)
+        fock.fock_energy_kmesh_backward(cell, kpts, C, W, one, [G[k] for k in range(nk)], ws=ws)
+
+    # one step takes tens of seconds: at most 2 timed steps after 1 warmup
+    steps, warmup = min(args.steps, 2), min(args.warmup, 1)
+    dt = run_steps(step, steps, warmup)
+    pairs = nk * nk * nb * nb
+    rec = {"value": pairs * steps / dt, "ms_per_step": 1e3 * dt / steps, "dtype": "f32", "steps": steps,
+           "warmup": warmup,
+           "config": {"workload": name, "description": WORKLOADS[name], "grid": list(n), "npw": s.npw,
+                      "ecut_fock": ecut if ecut > 0.0 else None, "kpoints": nk, "bands_per_k": nb, "pairs_per_step": pairs,
+                      "step": "E_x over the mesh (blocks k <= k' only, E_kk' = E_k'k) and dE/dconj(C)"},
+           "cpu_baseline": cpu or None}
+    if not args.no_trace:
+        tr = traced(fock, step, 1)
+        acc = {k: [TILE_BYTES[k] * N * 8 * tr[k][1], tr[k][1]] for k in TILE_BYTES if k in tr and tr[k][1]}
+        rec["roofline"] = roofline(tr, acc, 1, name)
+        rec["kernels"] = {k: {"ms_per_step": round(v[0], 4), "launches_per_step": v[1]} for k, v in tr.items() if v[1]}
+    return rec
+
+
 def band_loops(name, args, cpu):
     import torch
     from paper_1305_7313_amd import fock
@@ -514,6 +567,8 @@ def main():
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "data": "synthetic"}
     if wl in ("c2_fp64", "c3_fp32", "c3_fp64", "c2r_fp64", "c3r_fp32"):
         r = single_block(wl, args, cpu=not args.no_cpu_baseline)
+    elif wl in ("c5_fp32_grad", "c5r_fp32_grad"):
+        r = kmesh_grad(wl, args, cpu=not args.no_cpu_baseline)
     elif wl == "c2g_fp64":
         r = gamma_block(wl, args, cpu=not args.no_cpu_baseline)
     elif wl.startswith("cp_"):

@@ -398,9 +398,16 @@ constexpr PlaneTune plane_tune(int tbytes, int n2, int n3, int mode) {
     if (n2 == 48 && n3 == 48) return PlaneTune{384, false, 1};
     return PlaneTune{192, false, 1};
   }
-  if (n2 == 96 && n3 == 128) return p1 ? PlaneTune{512, true, 2} : inv ? PlaneTune{512, true, 1} : PlaneTune{1024, false, 1};
+  if (n2 == 96 && n3 == 128) {
+    if (p1) return PlaneTune{512, true, 2};
+    if (inv) return PlaneTune{512, true, 1};
+    return mode == PLANE_INV_MAC ? PlaneTune{512, false, 1} : PlaneTune{1024, false, 1};
+  }
   if (n2 == 96 && n3 == 96) return mac ? PlaneTune{384, false, 1} : inv ? PlaneTune{768, true, 1} : PlaneTune{768, false, 1};
-  if (n2 == 72 && n3 == 72) return p1 ? PlaneTune{720, false, 1} : inv ? PlaneTune{720, true, 2} : PlaneTune{576, false, 1};
+  if (n2 == 72 && n3 == 72) {
+    if (p1 || fwdmac || mirror) return PlaneTune{720, false, 1};
+    return inv ? PlaneTune{720, true, 2} : PlaneTune{576, false, 1};
+  }
   if (n2 == 64 && n3 == 64) return PlaneTune{512, false, 1};
   if (n2 == 48 && n3 == 64) return PlaneTune{256, false, 1};
   if (n2 == 48 && n3 == 48) return p1 ? PlaneTune{192, false, 1} : PlaneTune{384, false, 1};
