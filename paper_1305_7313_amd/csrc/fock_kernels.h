@@ -78,7 +78,7 @@ struct PlaneArgs {
 
 struct PencilArgs {
   void* x;             // [npairs or nb][N]
-  double* epart;       // energy partials [npairs][ngroups] or null
+  double* epart;       // energy partials [ngroups][npairs] (group-major) or null
   const void* tw1;     // twiddle table, length n1
   KernelParams kp;
   long long N;
@@ -525,7 +525,7 @@ __device__ __forceinline__ void pencil_body(const PencilArgs& A, int lid, unsign
     }
     if (A.epart) {
       const double tot = block_sum(esum, red);
-      if (t == 0) A.epart[(long long)pr * ngroups + g] = tot;
+      if (t == 0) A.epart[(long long)g * A.count + pr] = tot;
     }
     if constexpr (MODE == PENCIL_FKI) {
       exchange<P1, P0, CB, SPLIT, T>(v, smem, t);

@@ -21,10 +21,20 @@ __global__ void energy_tile_kernel(const double* __restrict__ epart, int ngroups
       else wgt += f[j] * g[i];
     }
     if (wgt == 0.0) continue;
-    double s = 0.0;
-    const double* e = epart + (long long)pr * ngroups;
-    for (int k = 0; k < ngroups; ++k) s += e[k];
-    acc += wgt * s;
+    // group-major partials (consecutive threads read consecutive words), four
+    // independent partial sums so that the loads overlap; fixed combination order
+    const int np = ti * tj;
+    const double* e = epart + pr;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int k = 0;
+    for (; k + 4 <= ngroups; k += 4) {
+      s0 += e[(long long)k * np];
+      s1 += e[(long long)(k + 1) * np];
+      s2 += e[(long long)(k + 2) * np];
+      s3 += e[(long long)(k + 3) * np];
+    }
+    for (; k < ngroups; ++k) s0 += e[(long long)k * np];
+    acc += wgt * ((s0 + s1) + (s2 + s3));
   }
   const double tot = block_sum(acc, red);
   if (threadIdx.x == 0) *tile_e = escale * tot;
