@@ -143,27 +143,36 @@ fock_status fock_energy_kmesh_backward(const fock_cell *cell, int32_t nk, const 
                                        const fock_orbs *sets, const double *grad_ex, void *const *grad, void *ws,
                                        size_t ws_bytes, void *stream);
 
-/* Batched form: several independent systems (cells with cubic grids of 24,
- * 48, 64, 72 or 96 points, any band counts), each a block of orbitals
- * applied to itself at q = 0: vx_out[s] = V_x[orbs[s]] orbs[s] (layout of
- * fock_apply, leading dimension orbs[s].ld).  The band-pair work of every
- * system runs in ONE persistent kernel (device work queue of plane, pencil
- * and multiply-accumulate units with per-segment dependency counters), and
- * the whole batch -- scheduler reset, orbital transforms, the persistent
- * kernel and the per-target finish -- is captured in one hipGraph.
- * Inputs (orbs[s].c, .w) and outputs are bound at creation; their contents
- * may change between replays.  The plan owns its device memory.
- * The schedule (pair-tile size, units per work ticket, persistent blocks per
- * compute unit) is chosen by timing the candidates on this batch, unless the
- * JSON tune cache (tune_cache, else $FOCK_TUNE_CACHE; NULL/empty: none) has
- * an entry for the batch signature; the choice is written back to it.
+/* Batched form: several independent systems, each an apply as fock_apply
+ * (occupied block occ[s], target block tgt[s], q[s]) on its own cell and
+ * grid; the band-group sums of section 5 for every system are scheduled
+ * together and the whole batch is captured in one hipGraph.  tgt == NULL:
+ * every system applies its block to itself; q == NULL: q = 0 for all.
+ * Occupied and target coefficients and weights are bound at creation (their
+ * contents may change between replays).  The plan owns its device memory,
+ * including its results.
+ * Two forms of the graph exist and the faster one on this batch is kept:
+ *  - every system's own per-shape kernel schedule, one after another;
+ *  - when every system is a block applied to itself at q = 0 on a cubic grid
+ *    of 24, 48, 64, 72 or 96 points: one persistent kernel for the band-pair
+ *    work of all systems (a device work queue of plane, pencil and
+ *    multiply-accumulate units with per-segment dependency counters).
+ * The choice (and the persistent kernel's pair-tile size, units per work
+ * ticket and blocks per compute unit) comes from timing the candidates,
+ * unless the JSON tune cache (tune_cache, else $FOCK_TUNE_CACHE; NULL/empty:
+ * none) has an entry for the batch signature; the choice is written back.
  * Creation synchronises the device (it runs the candidates). */
-fock_status fock_batch_plan_create(const fock_cell *cells, const fock_orbs *orbs, void *const *vx_out, int32_t nsys,
-                                   int32_t dtype, const char *tune_cache, void **plan);
-/* One replay of the captured graph on `stream` (asynchronous). */
-fock_status fock_batch_apply(void *plan, void *stream);
+fock_status fock_batch_plan_create(const fock_cell *cells, const fock_orbs *occ, const fock_orbs *tgt,
+                                   const double (*q)[3], int32_t nsys, int32_t dtype, const char *tune_cache,
+                                   void **plan);
+/* Replays the graph on the stream, then copies the results out (both stream
+ * ordered): vx_out[s] (device [tgt[s].nb][tgt[s].ld], entries p >= npw
+ * untouched; vx_out or an entry NULL: not copied) and ex_out[s] = the
+ * exchange energy of system s, 1/2 sum_j g_j Re <psi_j | V_x psi_j> with
+ * g = tgt[s].w (device FP64 [nsys]; NULL: not copied). */
+fock_status fock_batch_apply(void *plan, void *const *vx_out, double *ex_out, void *stream);
 /* Synchronises the device and reports a scheduler abort (a dependency wait
- * that exceeded its bound) as FOCK_E_HIP. */
+ * of the persistent kernel that exceeded its poll limit) as FOCK_E_HIP. */
 fock_status fock_batch_check(void *plan);
 /* JSON description of the chosen schedule (owned by the plan). */
 const char *fock_batch_plan_info(void *plan);

@@ -1164,8 +1164,15 @@ struct BatchPlanImpl {
   int device = 0, dtype = 0, nsys = 0, cus = 0;
   std::vector<std::shared_ptr<Plan>> plans;
   std::vector<fock_cell> cells;
-  std::vector<fock_orbs> orbs;
-  std::vector<void*> outs;
+  std::vector<fock_orbs> orbs;  // occupied blocks
+  std::vector<fock_orbs> tgt;   // target blocks
+  std::vector<double> q;        // [nsys][3]
+  std::vector<char> qzero;
+  bool persistent_ok = true;    // every system one block applied to itself at q = 0 on a cubic grid
+  std::vector<void*> outs;      // plan-owned [tgt.nb][tgt.ld] results
+  double* d_ex = nullptr;       // [nsys] energies
+  double* d_bandE = nullptr;    // per-band energy terms, systems one after another
+  std::vector<int> band_off;
   std::vector<void*> phi, acc;
   std::vector<void*> allocs;
   double* d_k0 = nullptr;
@@ -1282,14 +1289,29 @@ void batch_segments(const BatchPlanImpl& B, const BatchParams& prm, std::vector<
   *total = start;
 }
 
+// E_s = 1/2 sum_j g_j Re <psi_j | V_x psi_j> per system, from the results on
+// the sphere (the reciprocal-space energy of the block: for V_x built from the
+// occupied block with its occupations, <psi_j|V_x psi_j> = -Omega sum_i f_i
+// sum_G K |rho_ij(G)|^2).  Two fixed-order stages.
+template <typename T>
+fock_status batch_energies(BatchPlanImpl& B, hipStream_t s) {
+  for (int k = 0; k < B.nsys; ++k) {
+    const fock_orbs& t = B.tgt[k];
+    if (t.nb == 0) {
+      FX_HIP(launch_set_scalar(B.d_ex + k, 0.0, s));
+      continue;
+    }
+    double* part = B.d_bandE + B.band_off[k];
+    FX_HIP(launch_band_dot<T>(t.c, t.ld, B.outs[k], t.ld, B.plans[k]->npw, t.w, t.nb, part, s));
+    FX_HIP(launch_energy_final(part, t.nb, 0.5, B.d_ex + k, s));
+  }
+  return FOCK_OK;
+}
+
 template <typename T>
 fock_status batch_capture(BatchPlanImpl& B, const BatchParams& prm) {
-  std::vector<BatchSeg> segs;
-  long long total = 0;
-  batch_segments(B, prm, &segs, &total);
-  B.nseg = (int)segs.size();
-  B.total_units = total;
-  // scheduler tables (re-allocated per schedule; the previous graph is dropped first)
+  if (prm.mode == 0 && !B.persistent_ok) return fail(FOCK_E_ARG, "internal: persistent schedule not applicable");
+  // the previous graph is dropped first
   if (B.exec) {
     (void)hipGraphExecDestroy(B.exec);
     B.exec = nullptr;
@@ -1299,33 +1321,42 @@ fock_status batch_capture(BatchPlanImpl& B, const BatchParams& prm) {
     B.graph = nullptr;
   }
   fock_status st;
-  void* p = nullptr;
-  if ((st = B.alloc(&p, sizeof(BatchSeg) * segs.size())) != FOCK_OK) return st;
-  B.d_seg = static_cast<BatchSeg*>(p);
-  if ((st = B.alloc(&p, sizeof(int) * segs.size())) != FOCK_OK) return st;
-  B.d_done = static_cast<int*>(p);
-  FX_HIP(hipMemcpy(B.d_seg, segs.data(), sizeof(BatchSeg) * segs.size(), hipMemcpyHostToDevice));
+  long long total = 0;
   BatchArgs a{};
-  a.sys = B.d_sys;
-  a.seg = B.d_seg;
-  a.nseg = B.nseg;
-  a.total_units = total;
-  a.units_per_ticket = prm.units_per_ticket;
-  a.slots = B.d_slots;
-  a.ticket = B.d_ticket;
-  a.done = B.d_done;
-  a.abort_flag = B.d_abort;
-  a.spin_limit = 400000000ll;  // polls of ~0.1 us each: far beyond any real wait
-  const int occ = prm.blocks_per_cu >= 2 ? 2 : 1;
-  const int bpc_max = batch_blocks_per_cu<T>(occ);
-  const int bpc = prm.blocks_per_cu > 0 && prm.blocks_per_cu < bpc_max ? prm.blocks_per_cu : bpc_max;
-  const int grid = bpc * B.cus;
+  int occ = 1, bpc = 0, grid = 0;
+  if (prm.mode == 0) {
+    // scheduler tables (re-allocated per schedule)
+    std::vector<BatchSeg> segs;
+    batch_segments(B, prm, &segs, &total);
+    B.nseg = (int)segs.size();
+    B.total_units = total;
+    void* p = nullptr;
+    if ((st = B.alloc(&p, sizeof(BatchSeg) * segs.size())) != FOCK_OK) return st;
+    B.d_seg = static_cast<BatchSeg*>(p);
+    if ((st = B.alloc(&p, sizeof(int) * segs.size())) != FOCK_OK) return st;
+    B.d_done = static_cast<int*>(p);
+    FX_HIP(hipMemcpy(B.d_seg, segs.data(), sizeof(BatchSeg) * segs.size(), hipMemcpyHostToDevice));
+    a.sys = B.d_sys;
+    a.seg = B.d_seg;
+    a.nseg = B.nseg;
+    a.total_units = total;
+    a.units_per_ticket = prm.units_per_ticket;
+    a.slots = B.d_slots;
+    a.ticket = B.d_ticket;
+    a.done = B.d_done;
+    a.abort_flag = B.d_abort;
+    a.spin_limit = 400000000ll;  // polls of ~0.1 us each: far beyond any real wait
+    occ = prm.blocks_per_cu >= 2 ? 2 : 1;
+    const int bpc_max = batch_blocks_per_cu<T>(occ);
+    bpc = prm.blocks_per_cu > 0 && prm.blocks_per_cu < bpc_max ? prm.blocks_per_cu : bpc_max;
+    grid = bpc * B.cus;
+  }
   if (prm.mode == 1 && !B.kws) {
     size_t need = 0;
     for (int k = 0; k < B.nsys; ++k) {
       const Plan& P = *B.plans[k];
       const int ng = P.n[1] * P.n[2] / pencil_columns(P.n[0], (int)sizeof(T));
-      need = std::max(need, layout(P.N, (int)sizeof(cx<T>), ng, B.orbs[k].nb, B.orbs[k].nb).total);
+      need = std::max(need, layout(P.N, (int)sizeof(cx<T>), ng, B.orbs[k].nb, B.tgt[k].nb).total);
     }
     if ((st = B.alloc(&B.kws, need)) != FOCK_OK) return st;
     B.kws_bytes = need;
@@ -1336,22 +1367,21 @@ fock_status batch_capture(BatchPlanImpl& B, const BatchParams& prm) {
   TR.on = false;
   hipStream_t s = B.cap;
   auto body = [&]() -> fock_status {
-    FX_HIP(launch_batch_reset(B.d_ticket, B.d_done, B.nseg, B.d_abort, s));
     if (prm.mode == 1) {
       // each system's own per-shape schedule (the single-system path), in turn
-      const double q0[3] = {0.0, 0.0, 0.0};
       for (int k = 0; k < B.nsys; ++k) {
         const Plan& P = *B.plans[k];
         const int ng = P.n[1] * P.n[2] / pencil_columns(P.n[0], (int)sizeof(T));
-        const Layout L = layout(P.N, (int)sizeof(cx<T>), ng, B.orbs[k].nb, B.orbs[k].nb);
+        const Layout L = layout(P.N, (int)sizeof(cx<T>), ng, B.orbs[k].nb, B.tgt[k].nb);
         if (L.total > B.kws_bytes) return fail(FOCK_E_WORKSPACE, "batch workspace too small");
         const double s0 = -1.0 / (P.omega * (double)P.N * (double)P.N);
-        fock_status st2 = apply_impl<T>(&B.cells[k], P, q0, true, &B.orbs[k], &B.orbs[k],
+        fock_status st2 = apply_impl<T>(&B.cells[k], P, &B.q[3 * k], B.qzero[k] != 0, &B.orbs[k], &B.tgt[k],
                                         static_cast<char*>(B.kws), L, s, B.outs[k], s0, nullptr, nullptr);
         if (st2 != FOCK_OK) return st2;
       }
-      return FOCK_OK;
+      return batch_energies<T>(B, s);
     }
+    FX_HIP(launch_batch_reset(B.d_ticket, B.d_done, B.nseg, B.d_abort, s));
     for (int k = 0; k < B.nsys; ++k) {
       Engine<T> E(*B.plans[k], s);
       fock_status st2 = E.g0_constant(&B.cells[k], true, B.d_k0 + k, B.d_gbpart);
@@ -1367,7 +1397,7 @@ fock_status batch_capture(BatchPlanImpl& B, const BatchParams& prm) {
       fock_status st2 = E.finish(B.acc[k], B.orbs[k].nb, 0, B.outs[k], B.orbs[k].ld, s0, nullptr, nullptr);
       if (st2 != FOCK_OK) return st2;
     }
-    return FOCK_OK;
+    return batch_energies<T>(B, s);
   };
   hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
   if (e != hipSuccess) {
@@ -1497,7 +1527,8 @@ fock_status batch_tune_and_capture(BatchPlanImpl& B, const std::string& cache) {
   const bool tune = !(env && std::atoi(env) == 0);
   // FOCK_BATCH_MODE = 0 / 1 restricts the plan to one mode (no cache use)
   const char* me = std::getenv("FOCK_BATCH_MODE");
-  const int force_mode = me && (std::atoi(me) == 0 || std::atoi(me) == 1) ? std::atoi(me) : -1;
+  int force_mode = me && (std::atoi(me) == 0 || std::atoi(me) == 1) ? std::atoi(me) : -1;
+  if (!B.persistent_ok) force_mode = 1;  // only the per-shape schedules apply
   if (!tune) {
     best.mode = force_mode == 1 ? 1 : 0;
   } else if (force_mode >= 0 || !tune_cache_lookup(cache, key, &best)) {
@@ -1580,6 +1611,26 @@ fock_status batch_create(BatchPlanImpl& B, const std::string& cache) {
   const size_t cb = sizeof(cx<T>);
   fock_status st;
   void* p = nullptr;
+  // plan-owned results and energies (both schedules)
+  int nbands = 0;
+  for (int k = 0; k < B.nsys; ++k) {
+    const fock_orbs& t = B.tgt[k];
+    if ((st = B.alloc(&p, cb * (size_t)t.nb * (size_t)t.ld)) != FOCK_OK) return st;
+    B.outs.push_back(p);
+    B.band_off.push_back(nbands);
+    nbands += t.nb;
+    B.pairs += (long long)B.orbs[k].nb * t.nb;
+  }
+  if ((st = B.alloc(&p, sizeof(double) * B.nsys)) != FOCK_OK) return st;
+  B.d_ex = static_cast<double*>(p);
+  if ((st = B.alloc(&p, sizeof(double) * (size_t)std::max(nbands, 1))) != FOCK_OK) return st;
+  B.d_bandE = static_cast<double*>(p);
+  if ((st = B.alloc(&p, sizeof(int))) != FOCK_OK) return st;
+  B.d_abort = static_cast<int*>(p);
+  FX_HIP(hipMemset(B.d_abort, 0, sizeof(int)));
+  FX_HIP(hipStreamCreateWithFlags(&B.cap, hipStreamNonBlocking));
+  if (!B.persistent_ok) return batch_tune_and_capture<T>(B, cache);
+  // the persistent kernel's state
   long long nmax = 0;
   for (int k = 0; k < B.nsys; ++k) {
     const Plan& P = *B.plans[k];
@@ -1589,7 +1640,6 @@ fock_status batch_create(BatchPlanImpl& B, const std::string& cache) {
     if ((st = B.alloc(&ac, cb * P.N * (size_t)B.orbs[k].nb)) != FOCK_OK) return st;
     B.phi.push_back(ph);
     B.acc.push_back(ac);
-    B.pairs += (long long)B.orbs[k].nb * B.orbs[k].nb;
   }
   if ((st = B.alloc(&p, sizeof(double) * B.nsys)) != FOCK_OK) return st;
   B.d_k0 = static_cast<double*>(p);
@@ -1628,9 +1678,6 @@ fock_status batch_create(BatchPlanImpl& B, const std::string& cache) {
   FX_HIP(hipMemcpy(B.d_slots, B.slot_mem.data(), sizeof(void*) * max_slots, hipMemcpyHostToDevice));
   if ((st = B.alloc(&p, sizeof(unsigned long long))) != FOCK_OK) return st;
   B.d_ticket = static_cast<unsigned long long*>(p);
-  if ((st = B.alloc(&p, sizeof(int))) != FOCK_OK) return st;
-  B.d_abort = static_cast<int*>(p);
-  FX_HIP(hipStreamCreateWithFlags(&B.cap, hipStreamNonBlocking));
   return batch_tune_and_capture<T>(B, cache);
 }
 }  // namespace
@@ -1857,11 +1904,12 @@ fock_status fock_exchange_grid(const fock_cell* cell, int32_t nq, const double* 
   return FOCK_OK;
 }
 
-fock_status fock_batch_plan_create(const fock_cell* cells, const fock_orbs* orbs, void* const* vx_out, int32_t nsys,
-                                   int32_t dtype, const char* tune_cache, void** plan) {
+fock_status fock_batch_plan_create(const fock_cell* cells, const fock_orbs* occ, const fock_orbs* tgt,
+                                   const double (*q)[3], int32_t nsys, int32_t dtype, const char* tune_cache,
+                                   void** plan) {
   if (!plan) return fail(FOCK_E_ARG, "plan is NULL");
   *plan = nullptr;
-  if (nsys <= 0 || !cells || !orbs || !vx_out) return fail(FOCK_E_ARG, "need nsys > 0, cells, orbs and vx_out");
+  if (nsys <= 0 || !cells || !occ) return fail(FOCK_E_ARG, "need nsys > 0, cells and occ");
   if (dtype != FOCK_C128 && dtype != FOCK_C64) return fail(FOCK_E_ARG, "bad dtype");
   auto B = std::make_unique<BatchPlanImpl>();
   B->dtype = dtype;
@@ -1869,14 +1917,24 @@ fock_status fock_batch_plan_create(const fock_cell* cells, const fock_orbs* orbs
   fock_status st;
   for (int k = 0; k < nsys; ++k) {
     const fock_cell* c = &cells[k];
+    const fock_orbs& o = occ[k];
+    const fock_orbs& t = tgt ? tgt[k] : occ[k];
+    const double q0[3] = {0.0, 0.0, 0.0};
+    const double* qk = q ? q[k] : q0;
     if ((st = check_cell_host(c, dtype)) != FOCK_OK) return st;
-    if (!(c->n[0] == c->n[1] && c->n[1] == c->n[2]) ||
-        !(c->n[0] == 24 || c->n[0] == 48 || c->n[0] == 64 || c->n[0] == 72 || c->n[0] == 96))
-      return fail(FOCK_E_UNSUPPORTED_GRID, "batched systems need a cubic grid of 24, 48, 64, 72 or 96 points");
     if (!grid_supported(c->n, dtype)) return fail(FOCK_E_UNSUPPORTED_GRID, "unsupported grid " + grid_str(c->n));
-    if ((st = check_alias(c, nullptr, 0)) != FOCK_OK) return st;
-    if ((st = check_orbs(&orbs[k], c->npw, "orbs[k]")) != FOCK_OK) return st;
-    if (orbs[k].nb > 0 && !vx_out[k]) return fail(FOCK_E_ARG, "vx_out[k] is NULL");
+    if ((st = check_orbs(&o, c->npw, "occ[k]")) != FOCK_OK) return st;
+    if ((st = check_orbs(&t, c->npw, "tgt[k]")) != FOCK_OK) return st;
+    bool qz = true;
+    if ((st = check_q(c, qk, &qz)) != FOCK_OK) return st;
+    if ((st = check_alias(c, qk, 1)) != FOCK_OK) return st;
+    const bool self = o.c == t.c && o.nb == t.nb && o.ld == t.ld;
+    const bool cubic = c->n[0] == c->n[1] && c->n[1] == c->n[2] &&
+                       (c->n[0] == 24 || c->n[0] == 48 || c->n[0] == 64 || c->n[0] == 72 || c->n[0] == 96);
+    if (!(self && qz && cubic)) B->persistent_ok = false;
+    B->tgt.push_back(t);
+    B->q.insert(B->q.end(), qk, qk + 3);
+    B->qzero.push_back(qz ? 1 : 0);
   }
   if (hipGetDevice(&B->device) != hipSuccess) return fail(FOCK_E_HIP, "no HIP device available");
   hipDeviceProp_t prop{};
@@ -1889,8 +1947,7 @@ fock_status fock_batch_plan_create(const fock_cell* cells, const fock_orbs* orbs
     fock_cell c = cells[k];
     c.miller = nullptr;  // host memory of the caller: not kept
     B->cells.push_back(c);
-    B->orbs.push_back(orbs[k]);
-    B->outs.push_back(vx_out[k]);
+    B->orbs.push_back(occ[k]);
   }
   const char* env_cache = std::getenv("FOCK_TUNE_CACHE");
   const std::string cache = tune_cache ? tune_cache : (env_cache ? env_cache : "");
@@ -1900,11 +1957,25 @@ fock_status fock_batch_plan_create(const fock_cell* cells, const fock_orbs* orbs
   return FOCK_OK;
 }
 
-fock_status fock_batch_apply(void* plan, void* stream) {
+fock_status fock_batch_apply(void* plan, void* const* vx_out, double* ex_out, void* stream) {
   if (!plan) return fail(FOCK_E_ARG, "plan is NULL");
   BatchPlanImpl* B = static_cast<BatchPlanImpl*>(plan);
-  hipError_t e = hipGraphLaunch(B->exec, static_cast<hipStream_t>(stream));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = hipGraphLaunch(B->exec, s);
   if (e != hipSuccess) return fail(FOCK_E_HIP, std::string("hipGraphLaunch: ") + hipGetErrorString(e));
+  const size_t cb = B->dtype == FOCK_C128 ? 16 : 8;
+  for (int k = 0; vx_out && k < B->nsys; ++k) {
+    const fock_orbs& t = B->tgt[k];
+    if (!vx_out[k] || t.nb == 0) continue;
+    // rows of npw values at the targets' leading dimension; entries p >= npw untouched
+    e = hipMemcpy2DAsync(vx_out[k], cb * t.ld, B->outs[k], cb * t.ld, cb * B->plans[k]->npw, t.nb,
+                         hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return fail(FOCK_E_HIP, std::string("batch result copy: ") + hipGetErrorString(e));
+  }
+  if (ex_out) {
+    e = hipMemcpyAsync(ex_out, B->d_ex, sizeof(double) * B->nsys, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return fail(FOCK_E_HIP, std::string("batch energy copy: ") + hipGetErrorString(e));
+  }
   return FOCK_OK;
 }
 

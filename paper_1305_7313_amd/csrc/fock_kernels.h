@@ -722,6 +722,24 @@ __global__ void gather_unpack_kernel(const cx<T>* __restrict__ box, long long N,
   }
 }
 
+// part[b] = g[b] Re sum_p conj(c[b][p]) v[b][p]  (one block per band, FP64 sum):
+// with v = V_x psi, 1/2 sum_b part[b] is the exchange energy of the block.
+template <typename T>
+__global__ void band_dot_kernel(const cx<T>* __restrict__ c, int ldc, const cx<T>* __restrict__ v, int ldv, int npw,
+                                const double* __restrict__ g, double* __restrict__ part) {
+  __shared__ double red[4];
+  const int b = blockIdx.x;
+  const cx<T>* cb = c + (long long)b * ldc;
+  const cx<T>* vb = v + (long long)b * ldv;
+  double s = 0.0;
+  for (int p = threadIdx.x; p < npw; p += blockDim.x) {
+    const cx<T> x = cb[p], y = vb[p];
+    s += double(x.x) * double(y.x) + double(x.y) * double(y.y);
+  }
+  const double tot = block_sum(s, red);
+  if (threadIdx.x == 0) part[b] = g[b] * tot;
+}
+
 // Band force on the sphere:
 //   out[j][p] = -w[j0+j] * (1/2 |k+G_p|^2 c[j][p] + box[j][slot[p]] / N)
 struct ForceArgs {

@@ -29,6 +29,9 @@ hipError_t launch_scatter_pack(const void* c, int ldc, const int* slot, int npw,
 template <typename T>
 hipError_t launch_gather_unpack(const void* box, long long N, const int* slot, int npw, const int n[3], int nreal,
                                 void* out, int ldo, double s0, hipStream_t s);
+template <typename T>
+hipError_t launch_band_dot(const void* c, int ldc, const void* v, int ldv, int npw, const double* g, int nb,
+                           double* part, hipStream_t s);
 template <typename T> hipError_t launch_force_gather(const ForceArgs& a, int nj, hipStream_t s);
 hipError_t launch_group_sum(const double* part, int ngrp, long long N, double* rho, hipStream_t s);
 

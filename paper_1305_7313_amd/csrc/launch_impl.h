@@ -156,6 +156,15 @@ hipError_t launch_gather_unpack<FX_T>(const void* box, long long N, const int* s
 }
 
 template <>
+hipError_t launch_band_dot<FX_T>(const void* c, int ldc, const void* v, int ldv, int npw, const double* g, int nb,
+                                 double* part, hipStream_t s) {
+  if (nb <= 0) return hipSuccess;
+  hipLaunchKernelGGL(band_dot_kernel<FX_T>, dim3(nb), dim3(256), 0, s, reinterpret_cast<const cx<FX_T>*>(c), ldc,
+                     reinterpret_cast<const cx<FX_T>*>(v), ldv, npw, g, part);
+  return hipGetLastError();
+}
+
+template <>
 hipError_t launch_force_gather<FX_T>(const ForceArgs& a, int nj, hipStream_t s) {
   if (nj <= 0 || a.npw <= 0) return hipSuccess;
   const int bx = (a.npw + 255) / 256;

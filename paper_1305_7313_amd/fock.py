@@ -86,10 +86,10 @@ def lib():
                                                  P(fock_orbs), ctypes.c_void_p, P(ctypes.c_void_p),
                                                  ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
         L.fock_batch_plan_create.restype = ctypes.c_int
-        L.fock_batch_plan_create.argtypes = [P(fock_cell), P(fock_orbs), P(ctypes.c_void_p), ctypes.c_int32,
-                                             ctypes.c_int32, ctypes.c_char_p, P(ctypes.c_void_p)]
+        L.fock_batch_plan_create.argtypes = [P(fock_cell), P(fock_orbs), P(fock_orbs), P(ctypes.c_double * 3),
+                                             ctypes.c_int32, ctypes.c_int32, ctypes.c_char_p, P(ctypes.c_void_p)]
         L.fock_batch_apply.restype = ctypes.c_int
-        L.fock_batch_apply.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+        L.fock_batch_apply.argtypes = [ctypes.c_void_p, P(ctypes.c_void_p), ctypes.c_void_p, ctypes.c_void_p]
         L.fock_batch_check.restype = ctypes.c_int
         L.fock_batch_check.argtypes = [ctypes.c_void_p]
         L.fock_batch_plan_info.restype = ctypes.c_char_p
@@ -421,33 +421,44 @@ def fock_energy_kmesh_backward(cell: Cell, kpts, C, W, grad_ex, grad, ws=None):
 # batched form
 # ---------------------------------------------------------------------------
 class BatchPlan:
-    """Several systems, each a block of orbitals applied to itself at q = 0,
-    in one persistent launch captured in one hipGraph (C calls:
-    fock_batch_plan_create / _apply / _check / _plan_info / _plan_destroy).
-    The tensors passed here are bound to the graph and must stay alive."""
+    """Several systems, each an apply as fock_apply (occupied block, target
+    block, q), in one hipGraph (C calls: fock_batch_plan_create / _apply /
+    _check / _plan_info / _plan_destroy).  tgt_coeffs None: each block is
+    applied to itself; q None: q = 0.  The tensors passed here are bound to
+    the graph and must stay alive; apply() fills self.outs and self.ex."""
 
-    def __init__(self, cells, coeffs, weights, outs=None, tune_cache=None):
+    def __init__(self, cells, coeffs, weights, tgt_coeffs=None, tgt_weights=None, q=None, tune_cache=None):
         import torch
         n = len(cells)
         if not (len(coeffs) == len(weights) == n):
             raise ValueError("one coefficient block and one weight vector per cell")
+        if (tgt_coeffs is None) != (tgt_weights is None):
+            raise ValueError("target coefficients and weights go together")
         dt = dtype_code(coeffs[0])
-        if outs is None:
-            outs = [torch.empty((c.shape[0], cell.npw), dtype=c.dtype, device=c.device)
-                    for c, cell in zip(coeffs, cells)]
-        self.cells, self.coeffs, self.weights, self.outs = list(cells), list(coeffs), list(weights), list(outs)
+        self.cells, self.coeffs, self.weights = list(cells), list(coeffs), list(weights)
+        self.tgt_coeffs = list(tgt_coeffs) if tgt_coeffs is not None else self.coeffs
+        self.tgt_weights = list(tgt_weights) if tgt_weights is not None else self.weights
+        self.outs = [torch.empty_like(c) for c in self.tgt_coeffs]
+        self.ex = torch.empty(n, dtype=torch.float64, device=coeffs[0].device)
         cs = (fock_cell * n)(*[c.c for c in self.cells])
-        os_ = (fock_orbs * n)(*[orbs(c, w) for c, w in zip(self.coeffs, self.weights)])
-        ptrs = (ctypes.c_void_p * n)(*[o.data_ptr() if o.numel() else None for o in self.outs])
+        occ = (fock_orbs * n)(*[orbs(c, w) for c, w in zip(self.coeffs, self.weights)])
+        tgt = None
+        if tgt_coeffs is not None:
+            tgt = (fock_orbs * n)(*[orbs(c, w) for c, w in zip(self.tgt_coeffs, self.tgt_weights)])
+        qa = None
+        if q is not None:
+            q3 = ctypes.c_double * 3
+            qa = (q3 * n)(*[q3(*[float(x) for x in qq]) for qq in q])
         plan = ctypes.c_void_p()
         cache = tune_cache.encode() if tune_cache else None
-        _check(lib().fock_batch_plan_create(cs, os_, ptrs, n, dt, cache, ctypes.byref(plan)))
+        _check(lib().fock_batch_plan_create(cs, occ, tgt, qa, n, dt, cache, ctypes.byref(plan)))
         self._plan = plan
+        self._outp = (ctypes.c_void_p * n)(*[o.data_ptr() if o.numel() else None for o in self.outs])
 
     def apply(self, stream=None):
         import torch
         s = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream) if stream is None else stream
-        _check(lib().fock_batch_apply(self._plan, s))
+        _check(lib().fock_batch_apply(self._plan, self._outp, self.ex.data_ptr(), s))
         return self.outs
 
     def check(self):

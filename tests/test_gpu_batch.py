@@ -51,14 +51,17 @@ def test_batch_small_vs_single_and_oracle(prec, mode, tmp_path, monkeypatch):
     plan.apply()
     plan.check()
     outs = [host(o).copy() for o in plan.outs]
+    ex = host(plan.ex).copy()
     for k, (s, c, f, gb) in enumerate(systems):
         single = host(F.fock_apply(cells[k], (0, 0, 0), C[k], W[k], C[k]))
         k0 = exx.gb_constant(s.a, s.n, (2, 2, 2), 0.6) if gb else 0.0
         ref = exx.fock_apply(s.a, s.n, s.miller, np.zeros(3), c, f, c, k0=k0)
         e1, e2, e3 = rel_fro(outs[k], single), rel_fro(outs[k], ref), max_row_rel(outs[k], ref)
-        report(f"batch small {prec} system {k}", vs_single=e1, vs_oracle=e2, vs_oracle_maxband=e3)
+        e_ref = exx.fock_energy(s.a, s.n, s.miller, np.zeros(3), c, f, c, f, k0=k0)
+        e4 = abs(ex[k] - e_ref) / abs(e_ref)
+        report(f"batch small {prec} system {k}", vs_single=e1, vs_oracle=e2, vs_oracle_maxband=e3, E_rel=e4)
         # the tuned tile may group the accumulation differently from the single-system path
-        assert e1 < (1e-12 if prec == "c128" else 1e-6) and e2 < tol and e3 < tol
+        assert e1 < (1e-12 if prec == "c128" else 1e-6) and e2 < tol and e3 < tol and e4 < tol
     # replays with eager work and synchronisation in between: every replay equals the first
     for rep in range(3):
         junk = torch.randn(1 << 20, device="cuda").cumsum(0)
@@ -117,4 +120,52 @@ def test_batch_config4_fp32(mode, monkeypatch):
     err = rel_fro(host(plan.outs[k]), ref)
     report("config4", batched_vs_single_worst=worst, smallest_system_vs_oracle=err)
     assert worst < 1e-6 and err < 1e-5
+    plan.close()
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_batch_general_systems(prec, tmp_path):
+    """Occupied and target blocks that differ, q != 0, a non-cubic grid: the
+    persistent schedule does not apply and the plan uses per-shape kernels."""
+    import torch
+    F = _F()
+    cdt = torch.complex128 if prec == "c128" else torch.complex64
+    tol = 1e-10 if prec == "c128" else 1e-5
+    skew = np.array([[10.0, 0.0, 0.0], [1.0, 18.0, 0.0], [0.5, 0.3, 24.0]])
+    specs = [  # (cell, grid, n_occ, n_tgt or None (self), q)
+        (synth.cubic_cell(10.0), (24, 24, 24), 9, None, (0.0, 0.0, 0.0)),
+        (synth.cubic_cell(10.0), (24, 24, 24), 7, 5, (0.1, -0.05, 0.07)),
+        (skew, (24, 48, 64), 6, None, (0.03, 0.02, -0.04)),
+        (synth.cubic_cell(15.0), (48, 48, 48), 5, 11, (0.0, 0.0, 0.0)),
+    ]
+    cells, occ, focc, tgt, ftgt, qs, refs = [], [], [], [], [], [], []
+    for k, (a, n, no, nt, q) in enumerate(specs):
+        s = synth.make_system(a, n)
+        co = synth.random_orbitals(s.a, s.miller, no, 60 + k)
+        ct = co if nt is None else synth.random_orbitals(s.a, s.miller, nt, 70 + k)
+        rng = np.random.default_rng(80 + k)
+        fo = rng.uniform(0.3, 1.0, no)
+        ft = fo if nt is None else rng.uniform(0.3, 1.0, nt)
+        cells.append(F.Cell(s.a, s.n, s.miller))
+        occ.append(torch.from_numpy(co).to(cdt).cuda())
+        focc.append(torch.from_numpy(fo).cuda())
+        tgt.append(occ[-1] if nt is None else torch.from_numpy(ct).to(cdt).cuda())
+        ftgt.append(focc[-1] if nt is None else torch.from_numpy(ft).cuda())
+        qs.append(q)
+        refs.append((exx.fock_apply(s.a, s.n, s.miller, np.array(q), co, fo, ct),
+                     exx.fock_energy(s.a, s.n, s.miller, np.array(q), co, fo, ct, ft)))
+    print(f"[case] batch general {prec}", flush=True)
+    plan = F.BatchPlan(cells, occ, focc, tgt_coeffs=tgt, tgt_weights=ftgt, q=qs, tune_cache=str(tmp_path / "t.json"))
+    assert plan.info()["mode"] == "kernels"
+    for rep in range(2):
+        plan.apply()
+        plan.check()
+        ex = host(plan.ex)
+        for k in range(len(specs)):
+            v = host(plan.outs[k])
+            single = host(F.fock_apply(cells[k], qs[k], occ[k], focc[k], tgt[k]))
+            e1, e2 = rel_fro(v, refs[k][0]), rel_fro(v, single)
+            e3 = abs(ex[k] - refs[k][1]) / abs(refs[k][1])
+            report(f"batch general {prec} system {k} replay {rep}", vs_oracle=e1, vs_single=e2, E_rel=e3)
+            assert e1 < tol and e2 < 1e-12 and e3 < tol
     plan.close()
