@@ -191,3 +191,54 @@ def test_empty_blocks():
     assert float(host(F.fock_energy(cell, (0, 0, 0), co, f, empty, e0))) == 0.0
     out = F.fock_apply(cell, (0, 0, 0), co, f, empty)
     assert out.shape == (0, s.npw)
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_every_path_is_bitwise_reproducible(prec, monkeypatch):
+    """Device race check: two runs of each path give identical bits (the
+    self-application schedules 0-2, the Gamma path, the k-mesh energy and
+    gradient)."""
+    import torch
+    F = _F()
+    cdt = torch.complex128 if prec == "c128" else torch.complex64
+    s = synth.make_system(synth.cubic_cell(10.0), (24, 24, 24))
+    c = dev(synth.random_orbitals(s.a, s.miller, 37, 31), cdt)
+    g = dev(synth.gamma_orbitals(s.a, s.miller, 21, 32), cdt)
+    f = dev(np.random.default_rng(33).uniform(0.2, 1.0, 37))
+    cell = F.Cell(s.a, s.n, s.miller, g0=F.FOCK_G0_GB, gb_alpha=0.7, nq=(2, 2, 2))
+    print(f"[case] reproducibility {prec}", flush=True)
+    for sched in ("0", "1", "2"):
+        monkeypatch.setenv("FOCK_SYM_SCHEDULE", sched)
+        a = host(F.fock_apply(cell, (0, 0, 0), c, f, c))
+        b = host(F.fock_apply(cell, (0, 0, 0), c, f, c))
+        assert np.array_equal(a, b), sched
+    a = host(F.fock_apply_gamma(cell, g, f[:21].contiguous()))
+    b = host(F.fock_apply_gamma(cell, g, f[:21].contiguous()))
+    assert np.array_equal(a, b)
+    kpts = synth.kmesh_points(s.a, (2, 2, 2))
+    C = torch.stack([dev(synth.random_orbitals(s.a, s.miller, 3, 40 + k), cdt) for k in range(8)])
+    W = torch.full((8, 3), 1.0 / 8, dtype=torch.float64, device="cuda")
+    one = torch.ones((), dtype=torch.float64, device="cuda")
+    runs = []
+    for _ in range(2):
+        e = float(host(F.fock_energy_kmesh(cell, kpts, C, W)))
+        G = torch.empty_like(C)
+        F.fock_energy_kmesh_backward(cell, kpts, C, W, one, [G[k] for k in range(8)])
+        runs.append((e, host(G)))
+    assert runs[0][0] == runs[1][0] and np.array_equal(runs[0][1], runs[1][1])
+
+
+def test_nan_input_is_not_masked():
+    """A NaN coefficient surfaces as NaN in the results (no silent masking)."""
+    import torch
+    F = _F()
+    s = synth.make_system(synth.cubic_cell(10.0), (24, 24, 24))
+    co = synth.random_orbitals(s.a, s.miller, 6, 34)
+    co[2, 5] = np.nan
+    c = dev(co)
+    f = dev(np.ones(6))
+    cell = F.Cell(s.a, s.n, s.miller)
+    print("[case] NaN input", flush=True)
+    v = host(F.fock_apply(cell, (0, 0, 0), c, f, c))
+    e = float(host(F.fock_energy(cell, (0, 0, 0), c, f, c, f)))
+    assert np.isnan(v).any() and np.isnan(e)
