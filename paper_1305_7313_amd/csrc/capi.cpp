@@ -94,7 +94,7 @@ struct Plan {
   int* d_slot = nullptr;        // [npw] flat box index of each sphere G
   void* d_tw[3] = {nullptr, nullptr, nullptr};  // per axis, length n_a, dtype precision
   ~Plan() {
-    hipSetDevice(device);
+    (void)hipSetDevice(device);
     if (d_slot) (void)hipFree(d_slot);
     for (auto p : d_tw)
       if (p) (void)hipFree(p);
@@ -1196,7 +1196,7 @@ struct BatchPlanImpl {
   hipGraphExec_t exec = nullptr;
   std::string info;
   ~BatchPlanImpl() {
-    hipSetDevice(device);
+    (void)hipSetDevice(device);
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
     for (void* p : allocs) (void)hipFree(p);
