@@ -86,6 +86,17 @@ def _cpu_worker(j):
     return time.perf_counter() - t0
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(s, c, n=None, ecut=0.0, nocc=None):
     n = tuple(s.n if n is None else n)
     cores = len(os.sched_getaffinity(0))
@@ -102,7 +113,7 @@ def cpu_baseline(s, c, n=None, ecut=0.0, nocc=None):
         pool.map(_cpu_worker, range(workers))
         wall = time.perf_counter() - t0
     pairs = workers * nocc
-    return {"value": round(pairs / wall, 2), "unit": UNIT, "cores": workers, "kind": "oracle",
+    return {"value": round(pairs / wall, 2), "unit": UNIT, "cores": workers, "kind": "oracle", "cpu": cpu_model(),
             "sample": f"{workers} targets x first {nocc} occupied orbitals ({pairs} pairs) of the same workload, "
                       f"FP64 scipy FFT, one single-threaded process per target, wall {wall:.2f} s"}
 
@@ -133,7 +144,7 @@ def cpu_baseline_bands(s, c, w, v, force):
         pool.map(_band_worker, range(workers))
         wall = time.perf_counter() - t0
     nb = 8 * workers
-    return {"value": round(nb / wall, 2), "unit": "bands/s", "cores": workers, "kind": "oracle",
+    return {"value": round(nb / wall, 2), "unit": "bands/s", "cores": workers, "kind": "oracle", "cpu": cpu_model(),
             "sample": f"{nb} of the workload's bands, 8 per single-threaded process, FP64 scipy FFT, "
                       f"wall {wall:.2f} s"}
 
@@ -328,6 +339,9 @@ def single_block(name, args, cpu):
                       "pair_symmetry": "rho_ji = conj(rho_ij) reused; pairs counted as n_occ x n_tgt"},
            "cpu_baseline": cpu or None}
     rec["logical_hbm_gbs"] = round(rec["value"] * 4 * N * bpc / 1e9, 1)
+    # whole path against the HBM peak at the floor of 4 N b per pair (read both
+    # orbitals, read and write the accumulator)
+    rec["logical_frac"] = round(rec["logical_hbm_gbs"] / HBM_PEAK_GBS, 4)
     if not args.no_trace:
         tr = traced(fock, step, args.steps)
         acc = step_bytes(nb, N, bpc, fp64)
