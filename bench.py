@@ -157,8 +157,18 @@ def cpu_baseline_bands(s, c, w, v, force):
 # recomputed, nothing written back), FP32 the parallel inverse plus one pair
 # multiply-accumulate.
 # ---------------------------------------------------------------------------
-def step_bytes(nb, N, bpc, fp64, sym=True):
+def sym_schedule(fp64, n3):
+    """The library's default for one block applied to itself (FOCK_SYM_SCHEDULE overrides)."""
+    env = os.environ.get("FOCK_SYM_SCHEDULE")
+    if env in ("0", "1", "2"):
+        return int(env)
+    return 2 if fp64 and n3 <= 64 else 1
+
+
+def step_bytes(nb, N, bpc, fp64, sym=True, sched=None):
     T = min(MAC_TILE, nb)
+    if sched is None:
+        sched = 2 if fp64 else 1
     acc = {}
 
     def add(k, rd, wr, n=1):
@@ -175,8 +185,8 @@ def step_bytes(nb, N, bpc, fp64, sym=True):
             add("p2_pencil_kernel", ti * tj, ti * tj)
             if not sym:
                 add("p3_plane_inv_mac", ti * tj + ti + tj, tj)
-            elif fp64:  # schedule 2: fused P3 into acc_J, fused mirror pass into acc_I
-                add("p3_plane_inv_mac", ti * tj + ti + tj, tj)
+            elif sched in (0, 2):  # fused P3 into acc_J; mirror: recomputed (2) or from v written back (0)
+                add("p3_plane_inv_mac", ti * tj + ti + tj, tj + (ti * tj if sched == 0 and not diag else 0))
                 if not diag:
                     add("p3_second", ti * tj + tj + ti, ti)
             else:  # schedule 1: in-place inverse, one MAC for both halves
@@ -344,7 +354,7 @@ def single_block(name, args, cpu):
     rec["logical_frac"] = round(rec["logical_hbm_gbs"] / HBM_PEAK_GBS, 4)
     if not args.no_trace:
         tr = traced(fock, step, args.steps)
-        acc = step_bytes(nb, N, bpc, fp64)
+        acc = step_bytes(nb, N, bpc, fp64, sched=sym_schedule(fp64, n[2]))
         rec["roofline"] = roofline(tr, acc, args.steps, name)
         rec["kernels"] = {k: {"ms_per_step": round(v[0] / args.steps, 4), "launches_per_step": v[1] / args.steps}
                           for k, v in tr.items() if v[1]}

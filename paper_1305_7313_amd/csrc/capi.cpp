@@ -500,15 +500,21 @@ struct Engine {
   //   0  fused inverse FFT + MAC into acc_J, v_ij written back and streamed
   //      into acc_I by a second kernel;
   //   1  fully parallel in-place inverse FFT, then one MAC kernel for both
-  //      halves (default for FP32, whose transforms are VALU-bound);
+  //      halves (default for FP32, whose transforms are VALU-bound, and for
+  //      FP64 planes from 72 points wide);
   //   2  fused inverse FFT + MAC into acc_J, and a second fused pass that
   //      recomputes v_ij and accumulates the mirror into acc_I: no write-back,
-  //      one more transform (default for FP64, which is HBM-bound).
-  static int sym_schedule() {
+  //      one more transform (default for FP64 planes up to 64 points wide,
+  //      which are HBM-bound).
+  // The fused passes hold a plane of complex accumulators beside the plane
+  // being transformed; from 72 points wide in FP64 that exceeds the register
+  // budget and spills, and schedule 1 measured faster: 72^3 -18%, 96^3 -22%,
+  // 96 x 96 x 128 -51% per apply (48^3 and 64^3: schedule 2 faster by 6-16%).
+  int sym_schedule() const {
     const char* e = std::getenv("FOCK_SYM_SCHEDULE");
     const int env = e ? std::atoi(e) : -1;
     if (env >= 0 && env <= 2) return env;
-    return sizeof(T) == 8 ? 2 : 1;
+    return sizeof(T) == 8 && P.n[2] <= 64 ? 2 : 1;
   }
 
   // One band-pair job: occupied block A (real space, weights fA) against
