@@ -517,6 +517,18 @@ struct Engine {
     return sizeof(T) == 8 && P.n[2] <= 64 ? 2 : 1;
   }
 
+  // Gamma tiles: 0 = fused inverse plane FFT + MAC passes (forward, then a
+  // recomputing mirror); 1 = in-place inverse plane FFT of the tile, then one
+  // streaming pass for both halves.  The fused passes hold a whole plane per
+  // block; from 72-point-wide planes they spill (FP64) or lose occupancy
+  // (FP32), and the streaming schedule is faster in both precisions.
+  int gamma_schedule() const {
+    const char* e = std::getenv("FOCK_GAMMA_SCHEDULE");
+    const int env = e ? std::atoi(e) : -1;
+    if (env == 0 || env == 1) return env;
+    return std::max(P.n[1], P.n[2]) >= 72 ? 1 : 0;
+  }
+
   // One band-pair job: occupied block A (real space, weights fA) against
   // target block B.  energy: per-tile FP64 partials into tile_e[tile_base..];
   // apply with acc_full == null: per-target-tile accumulators, each finished
@@ -709,6 +721,7 @@ fock_status apply_impl(const fock_cell* cell, const Plan& P, const double q[3], 
 // targets packed per complex transform.  Packed tiles: 16 real occupied x 8
 // packed targets (16 real); only tiles that hold a pair i <= j run.
 constexpr int kGammaTi = 16, kGammaTj = 8;
+static_assert(kGammaTi <= kMacTile, "the streaming Gamma MAC holds one tile row per thread");
 
 template <typename T>
 fock_status apply_gamma_impl(const fock_cell* cell, const Plan& P, const fock_orbs* o, char* ws, const Layout& L,
@@ -741,6 +754,28 @@ fock_status apply_gamma_impl(const fock_cell* cell, const Plan& P, const fock_or
       PlaneArgs la = E.plane_args(pk, pk, ws + L.w, nullptr, o->w, i0, j0, ti, tj);
       la.nreal = n;
       if ((st = E.tile_forward(la, kp, false, nullptr, PLANE_PAIR_FWD_G)) != FOCK_OK) return st;
+      if (E.gamma_schedule() == 1) {
+        {
+          FX_TRACE(KC_P3);
+          PlaneArgs lv = E.plane_args(nullptr, nullptr, nullptr, nullptr, nullptr, 0, 0, 0, 0);
+          lv.x = ws + L.w;
+          lv.nb = ti * tj;
+          FX_HIP(launch_plane<T>(PLANE_INV, P.n[1], P.n[2], lv, ti * tj * P.n[0], s));
+        }
+        MacArgs ma{};
+        ma.w = ws + L.w;
+        ma.phi = pk;
+        ma.f = o->w;
+        ma.acc = acc;
+        ma.N = P.N;
+        ma.i0 = i0;
+        ma.j0 = j0;
+        ma.ti = ti;
+        ma.tj = tj;
+        FX_TRACE(KC_P3B);
+        FX_HIP(launch_mac_gamma<T>(ma, n, s));
+        continue;
+      }
       PlaneArgs lp = la;
       lp.acc = static_cast<char*>(acc) + (size_t)j0 * box;
       {

@@ -625,6 +625,66 @@ __global__ __launch_bounds__(256) void mac_pair_kernel(MacArgs A) {
   }
 }
 
+// Gamma tile with v_iq = v_{i,2q} + i v_{i,2q+1} in real space in the pair
+// buffer (slot ii * tj + jj): both halves in one streaming pass.  phi is the
+// packed orbital array, acc the packed accumulators; a pair (i, j) adds
+// f_i phi_i v_ij to acc_j when i <= j and f_j phi_j v_ij to acc_i when i < j
+// (component j mod 2 of packed accumulator j / 2).  One thread per grid point
+// owns every accumulator it touches, so diagonal tiles need no ordering.
+template <typename T>
+__global__ __launch_bounds__(256) void mac_gamma_kernel(MacArgs A, int nreal) {
+  const long long N = A.N;
+  const long long p = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (p >= N) return;
+  const cx<T>* __restrict__ w = reinterpret_cast<const cx<T>*>(A.w) + p;
+  const cx<T>* __restrict__ pk = reinterpret_cast<const cx<T>*>(A.phi) + p;
+  cx<T>* __restrict__ acc = reinterpret_cast<cx<T>*>(A.acc) + p;
+  const double* __restrict__ f = A.f;
+  const int ti = A.ti, tj = A.tj;
+  T phi_i[kMacTile], mir_i[kMacTile];
+#pragma unroll
+  for (int ii = 0; ii < kMacTile; ++ii) {
+    mir_i[ii] = T(0);
+    phi_i[ii] = T(0);
+    if (ii < ti) {
+      const int i = A.i0 + ii;
+      const cx<T> a = pk[(long long)(i >> 1) * N];
+      phi_i[ii] = (i & 1) ? a.y : a.x;
+    }
+  }
+  for (int jj = 0; jj < tj; ++jj) {
+    const int q = A.j0 + jj, j0r = 2 * q, j1r = 2 * q + 1;
+    const bool two = j1r < nreal;
+    const long long oq = (long long)q * N;
+    const cx<T> P = pk[oq];
+    const cx<T> a0 = acc[oq];
+    const T fj0 = T(f[j0r]), fj1 = two ? T(f[j1r]) : T(0);
+    T sx = a0.x, sy = a0.y;
+#pragma unroll
+    for (int ii = 0; ii < kMacTile; ++ii) {
+      if (ii < ti) {
+        const int i = A.i0 + ii;
+        const cx<T> v = w[(long long)(ii * tj + jj) * N];
+        const T fi = T(f[i]);
+        const T w0 = i <= j0r ? fi : T(0), w1 = (i <= j1r && two) ? fi : T(0);
+        sx += w0 * phi_i[ii] * v.x;
+        sy += w1 * phi_i[ii] * v.y;
+        const T m0 = i < j0r ? fj0 : T(0), m1 = (i < j1r && two) ? fj1 : T(0);
+        mir_i[ii] += m0 * P.x * v.x + m1 * P.y * v.y;
+      }
+    }
+    acc[oq] = mk<T>(sx, sy);
+  }
+#pragma unroll
+  for (int ii = 0; ii < kMacTile; ++ii) {
+    if (ii < ti) {
+      const int i = A.i0 + ii;
+      T* c = reinterpret_cast<T*>(acc + (long long)(i >> 1) * N) + (i & 1);
+      *c += mir_i[ii];
+    }
+  }
+}
+
 // Mirror half only (schedule with a fused P3 that left v_ij in the pair
 // buffer): acc_i += sum_j f_j phi_j conj(v_ij).  One block per (ii, i1).
 template <typename T>

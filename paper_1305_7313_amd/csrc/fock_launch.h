@@ -29,6 +29,7 @@ hipError_t launch_scatter_pack(const void* c, int ldc, const int* slot, int npw,
 template <typename T>
 hipError_t launch_gather_unpack(const void* box, long long N, const int* slot, int npw, const int n[3], int nreal,
                                 void* out, int ldo, double s0, hipStream_t s);
+template <typename T> hipError_t launch_mac_gamma(const MacArgs& a, int nreal, hipStream_t s);
 template <typename T>
 hipError_t launch_band_dot(const void* c, int ldc, const void* v, int ldv, int npw, const double* g, int nb,
                            double* part, hipStream_t s);

@@ -156,6 +156,13 @@ hipError_t launch_gather_unpack<FX_T>(const void* box, long long N, const int* s
 }
 
 template <>
+hipError_t launch_mac_gamma<FX_T>(const MacArgs& a, int nreal, hipStream_t s) {
+  const long long blocks = (a.N + 255) / 256;
+  hipLaunchKernelGGL(mac_gamma_kernel<FX_T>, dim3((unsigned)blocks), dim3(256), 0, s, a, nreal);
+  return hipGetLastError();
+}
+
+template <>
 hipError_t launch_band_dot<FX_T>(const void* c, int ldc, const void* v, int ldv, int npw, const double* g, int nb,
                                  double* part, hipStream_t s) {
   if (nb <= 0) return hipSuccess;

@@ -4,7 +4,8 @@ CPU FP64 oracle and against the general path on the same orbitals.
 Bars: FP64 within 1e-10 relative, FP32 within 1e-5.  Cases cover odd and
 even band counts (ragged packed tiles), diagonal-tile masking, a skewed cell
 on a non-cubic grid with the Gygi-Baldereschi G = 0 term, the smallest
-blocks, and the benchmark's full-size workload.
+blocks, wide planes (both tile schedules, which must agree), and the
+benchmark's full-size workload.
 """
 import numpy as np
 import pytest
@@ -23,6 +24,10 @@ CASES = {
     "skew_gb": dict(a=SKEW, n=(24, 48, 64), nb=20, g0=1),
     "one": dict(a=synth.cubic_cell(10.0), n=(24, 24, 24), nb=1, g0=0),
     "two": dict(a=synth.cubic_cell(10.0), n=(24, 24, 24), nb=2, g0=1),
+    # wide planes: FP64 from 72 points and every 96x128 plane take the
+    # in-place inverse + streaming MAC schedule
+    "wide72": dict(a=np.diag([10.0, 30.0, 30.0]), n=(24, 72, 72), nb=19, g0=0),
+    "wide128": dict(a=SKEW, n=(24, 96, 128), nb=12, g0=1),
 }
 
 
@@ -85,3 +90,22 @@ def test_gamma_full_size():
     report("gamma full size", **errs)
     for k, val in errs.items():
         assert val < TOL["c128"], (k, val)
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_gamma_schedules_agree(prec, monkeypatch):
+    """Fused and streaming tile schedules on the same wide-plane system."""
+    F = _F()
+    s = synth.make_system(np.diag([10.0, 30.0, 30.0]), (24, 72, 72))
+    coef = synth.gamma_orbitals(s.a, s.miller, 21, 8)
+    f = np.random.default_rng(9).uniform(0.2, 1.0, 21)
+    cell = F.Cell(s.a, s.n, s.miller)
+    cd, fd = dev(coef, _ctype(prec)), dev(f)
+    out = {}
+    for sched in ("0", "1"):
+        print(f"[case] gamma schedule {sched} {prec}", flush=True)
+        monkeypatch.setenv("FOCK_GAMMA_SCHEDULE", sched)
+        out[sched] = host(F.fock_apply_gamma(cell, cd, fd))
+    err = rel_fro(out["1"], out["0"])
+    report(f"gamma schedules {prec}", rel=err)
+    assert err < TOL[prec]
