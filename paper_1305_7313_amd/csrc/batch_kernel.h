@@ -116,7 +116,7 @@ __device__ __forceinline__ void batch_mac_unit(const MacArgs& A, long long p0) {
 
 template <typename T, int NN> struct BatchShape {
   static constexpr int CB = pencil_tune(sizeof(T), NN).cb;
-  static constexpr bool PSPLIT = sizeof(T) == 8 && Tile<NN, plane_tile_pad<T, NN>()>::slots(NN) * 16 > 65536;
+  static constexpr bool PSPLIT = sizeof(T) == 8 && plane_slots<NN, plane_tile_pad<T, NN>()>(NN) * 16 > 65536;
   static constexpr bool CSPLIT = sizeof(T) == 8 && Tile<CB>::slots(NN) * 16 > 65536;
   static constexpr int XBYTES_P = PlaneGeom<T, NN, NN, kBatchW, PSPLIT>::XBYTES;
   static constexpr int XBYTES_C = PencilGeom<T, NN, CB, kBatchW, CSPLIT>::XBYTES;

@@ -321,27 +321,47 @@ __device__ __forceinline__ void pass_compute(cx<T>* v, const cx<T>* tw, int t) {
   }
 }
 
-// LDS tile of ROWS x COLS values.
-// PAD = false (pencil tiles, whose lanes walk consecutive columns): row
-//   stride COLS + 1.
-// PAD = true (plane tiles, where chosen): one spare word after every 8
-//   columns, so column c sits at c + c / 8, and a row stride from a small
-//   per-width table.  The first pass of a row transform writes column 8i + r
-//   from lane i, a stride of 8 words that lands many lanes in one bank;
-//   padded, lane i writes word 9i + r.  The padding keeps every element
-//   address an affine function of the lane (its offsets still fold into
-//   instruction immediates).  Widths and strides were chosen with a model of
-//   every exchange instruction's lane addresses over 32 and 64 banks of 4
-//   bytes: it cuts the conflict cycles of the 96 x 128 plane by 47% and of
-//   the 96 x 96 plane by 33%.
-constexpr int tile_pad_extra(int cols) {
-  return cols == 128 ? 8 : cols == 72 ? 7 : cols == 48 ? 2 : cols == 24 ? 1 : 0;
+// LDS tile of ROWS x COLS values for one exchange.  The layout is chosen per
+// exchange kind, since each exchange writes and reads its tile between two
+// barriers and owes nothing to the layout of the previous one.
+//   XK_PLAIN  pencil tiles and the compact plane tiles: row stride COLS + 1.
+//   XK_RR     row pass to row pass: one spare element after every 8 columns
+//             (column c at c + c / 8) and a row stride from a per-width
+//             table.  The first pass of a row transform writes column 8i + r
+//             from lane i, a stride of 8 elements that lands many lanes in
+//             one bank; padded, lane i writes element 9i + r.
+//   XK_RC, XK_CR, XK_CC  exchanges with a column pass on either side: plain
+//             rows (a column pass walks consecutive columns, which padding
+//             every 8 would wrap into the banks of the first ones) with a
+//             per-width row stride.
+// Every element address stays an affine function of the lane, so the
+// per-element offsets fold into instruction immediates.  The strides come
+// from a model of every exchange instruction's lane addresses, served 128 or
+// 256 bytes per cycle over banks of 4 bytes, for 8- and 16-byte elements; the
+// largest stays within the padded tile, so the LDS footprint is unchanged.
+enum XKind { XK_PLAIN = 0, XK_RR = 1, XK_RC = 2, XK_CR = 3, XK_CC = 4 };
+
+constexpr int tile_stride(int cols, int kind) {
+  switch (kind) {
+    case XK_RR:
+      return cols + cols / 8 + (cols == 128 ? 8 : cols == 72 ? 7 : cols == 48 ? 2 : 0);
+    case XK_RC:
+      return cols == 128 ? 136 : cols == 96 ? 104 : cols == 64 ? 72 : cols == 48 ? 56 : cols;
+    case XK_CR:
+      return cols == 128 ? 144 : cols == 96 ? 108 : cols == 72 ? 73 : cols == 64 ? 72 : cols == 48 ? 54
+                                                                                 : cols == 24 ? 27 : cols + 1;
+    case XK_CC:
+      return cols;
+    default:
+      return cols + 1;
+  }
 }
-template <int COLS, bool PAD = false> struct Tile {
-  static_assert(!PAD || COLS % 8 == 0, "padding every 8 columns");
-  static constexpr int SL = PAD ? COLS + COLS / 8 + tile_pad_extra(COLS) : COLS + 1;
+
+template <int COLS, int KIND = XK_PLAIN> struct Tile {
+  static_assert(KIND != XK_RR || COLS % 8 == 0, "padding every 8 columns");
+  static constexpr int SL = tile_stride(COLS, KIND);
   __device__ static __forceinline__ int at(int row, int col) {
-    if constexpr (PAD)
+    if constexpr (KIND == XK_RR)
       return row * SL + col + (col >> 3);
     else
       return row * SL + col;
@@ -349,12 +369,34 @@ template <int COLS, bool PAD = false> struct Tile {
   static constexpr int slots(int rows) { return rows * SL; }
 };
 
+// Exchange kind between pass A and pass B; PAD = false keeps XK_PLAIN.
+template <class PA, class PB, bool PAD> constexpr int exchange_kind() {
+  if constexpr (!PAD) return XK_PLAIN;
+  else if constexpr (PA::ROW && PB::ROW) return XK_RR;
+  else if constexpr (PA::ROW) return XK_RC;
+  else if constexpr (PB::ROW) return XK_CR;
+  else return XK_CC;
+}
+
+// Elements of LDS a plane tile of ROWS x COLS needs over all its exchanges.
+template <int COLS, bool PAD> constexpr int plane_slots(int rows) {
+  if constexpr (!PAD) {
+    return Tile<COLS>::slots(rows);
+  } else {
+    int m = Tile<COLS, XK_RR>::slots(rows);
+    m = Tile<COLS, XK_RC>::slots(rows) > m ? Tile<COLS, XK_RC>::slots(rows) : m;
+    m = Tile<COLS, XK_CR>::slots(rows) > m ? Tile<COLS, XK_CR>::slots(rows) : m;
+    m = Tile<COLS, XK_CC>::slots(rows) > m ? Tile<COLS, XK_CC>::slots(rows) : m;
+    return m;
+  }
+}
+
 // Move the outputs of pass A (in registers) to the inputs of pass B through
 // an LDS tile of COLS columns.  SPLIT exchanges real and imaginary parts in
 // two rounds so that an FP64 tile needs only 8 bytes of LDS per element.
 template <class PA, class PB, int COLS, bool SPLIT, typename T, bool PAD = false>
 __device__ __forceinline__ void exchange(cx<T>* v, void* smem, int t) {
-  using TL = Tile<COLS, PAD>;
+  using TL = Tile<COLS, exchange_kind<PA, PB, PAD>()>;
   if constexpr (!SPLIT) {
     cx<T>* buf = reinterpret_cast<cx<T>*>(smem);
     for_outputs<PA>(t, [&](int e, int row, int col) { buf[TL::at(row, col)] = v[e]; });

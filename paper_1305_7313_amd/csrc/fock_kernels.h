@@ -119,16 +119,15 @@ __device__ __forceinline__ int signed_index(int i, int n) { return i < (n >> 1) 
 // ---------------------------------------------------------------------------
 
 // Plane body: W threads, SPLIT selects the 8-byte (two-round) LDS exchange.
-// Padded LDS tiles (fft_engine.h, Tile) for the planes where they measured
-// faster: FP64 (64^3: -9% per apply) and 128-wide rows.  FP32 planes of
-// other widths keep the compact tile: the padding buys them nothing and on
-// the 96 x 96 plane it costs the second resident workgroup per CU (+15%).
-template <typename T, int N3> constexpr bool plane_tile_pad() { return sizeof(T) == 8 || N3 == 128; }
+// Per-exchange LDS layouts (fft_engine.h, Tile) on every plane but the FP32
+// 96 x 96 one, which keeps the compact tile: the larger one costs it the
+// second resident workgroup per CU (+15%).
+template <typename T, int N3> constexpr bool plane_tile_pad() { return !(sizeof(T) == 4 && N3 == 96); }
 
 template <typename T, int N2, int N3, int W, bool SPLIT> struct PlaneGeom {
   static constexpr int PLANE = N2 * N3;
   static constexpr int XBYTES =
-      Tile<N3, plane_tile_pad<T, N3>()>::slots(N2) * (SPLIT ? (int)sizeof(T) : 2 * (int)sizeof(T));
+      plane_slots<N3, plane_tile_pad<T, N3>()>(N2) * (SPLIT ? (int)sizeof(T) : 2 * (int)sizeof(T));
   using Rw = Axis<N3, N2, true, W>;   // transforms along i3, one per row
   using Cl = Axis<N2, N3, false, W>;  // transforms along i2, one per column
   static constexpr int NV = Rw::NV > Cl::NV ? Rw::NV : Cl::NV;
