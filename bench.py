@@ -181,18 +181,22 @@ def step_bytes(nb, N, bpc, fp64, sym=True, sched=None):
         for i0 in range(0, (j0 + 1) if sym else nb, T):
             ti = min(T, nb - i0)
             diag = sym and i0 == j0
-            add("p1_pair_plane_fwd", ti + (0 if diag else tj), ti * tj)
-            add("p2_pencil_kernel", ti * tj, ti * tj)
+            # diagonal tiles of schedules 1 and 2 hold only the pairs ii <= jj
+            tri = diag and sched != 0
+            npr = ti * (ti + 1) // 2 if tri else ti * tj
+            add("p1_pair_plane_fwd", ti + (0 if diag else tj), npr)
+            add("p2_pencil_kernel", npr, npr)
             if not sym:
                 add("p3_plane_inv_mac", ti * tj + ti + tj, tj)
             elif sched in (0, 2):  # fused P3 into acc_J; mirror: recomputed (2) or from v written back (0)
-                add("p3_plane_inv_mac", ti * tj + ti + tj, tj + (ti * tj if sched == 0 and not diag else 0))
+                add("p3_plane_inv_mac", npr + ti + tj, tj + (ti * tj if sched == 0 and not diag else 0))
                 if not diag:
                     add("p3_second", ti * tj + tj + ti, ti)
+                elif tri and ti > 1:
+                    add("p3_second", ti * (ti - 1) // 2 + tj + ti, ti)
             else:  # schedule 1: in-place inverse, one MAC for both halves
-                add("p3_plane_inv_mac", ti * tj, ti * tj)
-                add("p3_second", ti * tj + ti + (0 if diag else tj) + tj + (0 if diag else ti),
-                    tj + (0 if diag else ti))
+                add("p3_plane_inv_mac", npr, npr)
+                add("p3_second", npr + ti + (0 if diag else tj) + tj + ti, tj + (0 if diag and not tri else ti))
     return acc
 
 

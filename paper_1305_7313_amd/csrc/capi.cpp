@@ -461,7 +461,7 @@ struct Engine {
   // P1 and P2 of one pair tile (energy: P2 only accumulates partials).
   fock_status tile_forward(const PlaneArgs& la, const KernelParams& kp, bool energy, double* epart,
                            int p1_mode = PLANE_PAIR_FWD) {
-    const int tt = la.ti * la.tj;
+    const int tt = la.tri ? tri_slot(0, la.ti) : la.ti * la.tj;
     {
       FX_TRACE(KC_P1);
       FX_HIP(launch_plane<T>(p1_mode, P.n[1], P.n[2], la, tt * P.n[0], s));
@@ -599,6 +599,10 @@ struct Engine {
       for (int i0 = 0; i0 <= j0; i0 += T0, ++tile) {
         const int ti = (J.nA - i0) < T0 ? (J.nA - i0) : T0;
         PlaneArgs la = plane_args(phiA, phiA, w, nullptr, J.fA, i0, j0, ti, tj);
+        // diagonal tiles of an apply transform only the pairs ii <= jj
+        // (schedules 1 and 2); the mirror supplies the rest
+        la.tri = !J.energy && i0 == j0 && ti == tj && sym_schedule() != 0;
+        const int tt = la.tri ? tri_slot(0, ti) : ti * tj;
         if ((st = tile_forward(la, kp, J.energy, epart)) != FOCK_OK) return st;
         if (J.energy) {
           FX_TRACE(KC_REDUCE);
@@ -615,7 +619,7 @@ struct Engine {
             FX_TRACE(KC_P3);
             FX_HIP(launch_plane<T>(PLANE_INV_MAC, P.n[1], P.n[2], lp, tj * P.n[0], s));
           }
-          if (i0 != j0) {
+          if (i0 != j0 || (la.tri && ti > 1)) {
             PlaneArgs lb = lp;
             lb.acc = static_cast<char*>(acc_all) + (size_t)i0 * box;
             FX_TRACE(KC_P3B);
@@ -646,8 +650,8 @@ struct Engine {
           FX_TRACE(KC_P3);
           PlaneArgs lv = plane_args(nullptr, nullptr, nullptr, nullptr, nullptr, 0, 0, 0, 0);
           lv.x = w;
-          lv.nb = ti * tj;
-          FX_HIP(launch_plane<T>(PLANE_INV, P.n[1], P.n[2], lv, ti * tj * P.n[0], s));
+          lv.nb = tt;
+          FX_HIP(launch_plane<T>(PLANE_INV, P.n[1], P.n[2], lv, tt * P.n[0], s));
         }
         MacArgs ma{};
         ma.w = w;
@@ -659,7 +663,8 @@ struct Engine {
         ma.j0 = j0;
         ma.ti = ti;
         ma.tj = tj;
-        ma.mirror = i0 != j0;
+        ma.mirror = i0 != j0 || la.tri;
+        ma.tri = la.tri;
         FX_TRACE(KC_P3B);
         FX_HIP(launch_mac_pair<T>(ma, s));
       }

@@ -74,7 +74,12 @@ struct PlaneArgs {
   int accumulate;      // PLANE_DENS: add to part (else overwrite)
   const void* vloc;    // PLANE_VMUL: real potential V(r) [N], path precision
   int nreal;           // Gamma modes: number of real orbitals (packed arrays hold ceil(nreal / 2))
+  int tri;             // diagonal tile of a self-application (i0 == j0, ti == tj): only the
+                       // pairs ii <= jj, pair buffer slot tri_slot(ii, jj)
 };
+
+// Slot of pair (ii, jj), ii <= jj, in the pair buffer of a diagonal tile.
+__host__ __device__ constexpr int tri_slot(int ii, int jj) { return jj * (jj + 1) / 2 + ii; }
 
 struct PencilArgs {
   void* x;             // [npairs or nb][N]
@@ -148,9 +153,18 @@ __device__ __forceinline__ void plane_body(const PlaneArgs& A, int lid, unsigned
   cx<T> v[Cfg::NV];
 
   if constexpr (MODE == PLANE_PAIR_FWD || MODE == PLANE_PAIR_FWD_G) {
-    const int tt = A.ti * A.tj;
+    // workgroup (i1, slot): slot = ii * tj + jj, or tri_slot(ii, jj) on a diagonal tile
+    const int tt = A.tri ? A.ti * (A.ti + 1) / 2 : A.ti * A.tj;
     const int i1 = lid / tt, rem = lid - i1 * tt;
-    const int ii = rem / A.tj, jj = rem - ii * A.tj;
+    int ii, jj;
+    if (A.tri) {
+      jj = 0;
+      while (tri_slot(0, jj + 1) <= rem) ++jj;
+      ii = rem - tri_slot(0, jj);
+    } else {
+      ii = rem / A.tj;
+      jj = rem - ii * A.tj;
+    }
     const cx<T>* pb = reinterpret_cast<const cx<T>*>(A.bsrc) + (long long)(A.j0 + jj) * N + (long long)i1 * PLANE;
     if constexpr (MODE == PLANE_PAIR_FWD) {
       const cx<T>* pa = reinterpret_cast<const cx<T>*>(A.a) + (long long)(A.i0 + ii) * N + (long long)i1 * PLANE;
@@ -176,22 +190,25 @@ __device__ __forceinline__ void plane_body(const PlaneArgs& A, int lid, unsigned
     pass_compute<C0, -1, T>(v, tw2, t);
     exchange<C0, C1, N3, SPLIT, T, PAD>(v, smem, t);
     pass_compute<C1, -1, T>(v, tw2, t);
-    cx<T>* pw = reinterpret_cast<cx<T>*>(A.w) + (long long)(ii * A.tj + jj) * N + (long long)i1 * PLANE;
+    cx<T>* pw = reinterpret_cast<cx<T>*>(A.w) + (long long)rem * N + (long long)i1 * PLANE;
     for_outputs<C1>(t, [&](int e, int row, int col) { pw[row * N3 + col] = v[e]; });
   } else if constexpr (MODE == PLANE_INV_MAC || MODE == PLANE_INV_MAC_MIR) {
     // PLANE_INV_MAC: block (jj, i1), loop over ii, acc_j += f_i phi_i v_ij.
     // PLANE_INV_MAC_MIR (one orbital block at q = 0): block (ii, i1), loop over
     // jj, acc_i += f_j phi_j conj(v_ij), since v_ji = conj(v_ij).
+    // On a diagonal tile (tri) the forward pass takes ii <= jj and the mirror
+    // ii < jj, so each unordered pair reaches each accumulator once.
     constexpr bool mir = MODE == PLANE_INV_MAC_MIR;
     const int nblk = mir ? A.ti : A.tj, nloop = mir ? A.tj : A.ti;
     const int i1 = lid / nblk, bi = lid - (lid / nblk) * nblk;
     const int o0 = mir ? A.j0 : A.i0;
     const cx<T>* src = reinterpret_cast<const cx<T>*>(mir ? A.bsrc : A.a);
+    const int k0 = A.tri && mir ? bi + 1 : 0, k1 = A.tri && !mir ? bi + 1 : nloop;
     cx<T> s[R1::NV];
 #pragma unroll
     for (int e = 0; e < R1::NV; ++e) s[e] = mk<T>(T(0), T(0));
-    for (int k = 0; k < nloop; ++k) {
-      const int slot = mir ? bi * A.tj + k : k * A.tj + bi;
+    for (int k = k0; k < k1; ++k) {
+      const int slot = A.tri ? (mir ? tri_slot(bi, k) : tri_slot(k, bi)) : (mir ? bi * A.tj + k : k * A.tj + bi);
       const cx<T>* pw = reinterpret_cast<const cx<T>*>(A.w) + (long long)slot * N + (long long)i1 * PLANE;
       for_inputs<C0>(t, [&](int e, int row, int col) { v[e] = pw[row * N3 + col]; });
       pass_compute<C0, +1, T>(v, tw2, t);
@@ -569,6 +586,7 @@ struct MacArgs {
   void* acc;           // accumulators [n][N]
   long long N;
   int i0, j0, ti, tj, mirror;
+  int tri;             // diagonal tile: pairs ii <= jj at tri_slot(ii, jj); forward ii <= jj, mirror ii < jj
 };
 
 constexpr int kMacTile = 16;
@@ -582,7 +600,7 @@ __global__ __launch_bounds__(256) void mac_pair_kernel(MacArgs A) {
   const cx<T>* __restrict__ phi = reinterpret_cast<const cx<T>*>(A.phi) + p;
   cx<T>* __restrict__ acc = reinterpret_cast<cx<T>*>(A.acc) + p;
   const double* __restrict__ f = A.f;
-  const int ti = A.ti, tj = A.tj, mirror = A.mirror;
+  const int ti = A.ti, tj = A.tj, mirror = A.mirror, tri = A.tri;
   cx<T> fphi_i[kMacTile], acc_i[kMacTile];
 #pragma unroll
   for (int ii = 0; ii < kMacTile; ++ii) {
@@ -593,18 +611,19 @@ __global__ __launch_bounds__(256) void mac_pair_kernel(MacArgs A) {
     const long long oj = (long long)(A.j0 + jj) * N;
     const cx<T> aj0 = acc[oj];
     const cx<T> fphi_j = cscale<T>(phi[oj], T(f[A.j0 + jj]));
+    const int iend = tri ? jj + 1 : ti;  // forward: ii < iend; mirror: ii < jj on a diagonal tile
     cx<T> v[kMacTile];
 #pragma unroll
     for (int ii = 0; ii < kMacTile; ++ii)
-      if (ii < ti) v[ii] = w[(long long)(ii * tj + jj) * N];
+      if (ii < iend) v[ii] = w[(long long)(tri ? tri_slot(ii, jj) : ii * tj + jj) * N];
     T sx = aj0.x, sy = aj0.y;
 #pragma unroll
     for (int ii = 0; ii < kMacTile; ++ii) {
-      if (ii < ti) {
+      if (ii < iend) {
         const cx<T> a = cmul<T>(fphi_i[ii], v[ii]);
         sx += a.x;
         sy += a.y;
-        if (mirror) {
+        if (mirror && (!tri || ii < jj)) {
           const cx<T> m = cmulc<T>(v[ii], fphi_j);  // conj(v) f_j phi_j
           acc_i[ii] = mk<T>(acc_i[ii].x + m.x, acc_i[ii].y + m.y);
         }

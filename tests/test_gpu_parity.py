@@ -86,6 +86,10 @@ CASES = {
                         self=True),
     "self_gb_skew": dict(a=np.array([[10.0, 0.0, 0.0], [1.0, 18.0, 0.0], [0.5, 0.3, 24.0]]), n=(24, 48, 64),
                          nocc=20, ntgt=20, q=(0.0, 0.0, 0.0), g0=1, self=True),
+    # diagonal tiles of one orbital: the last of 17, and a single orbital
+    "self_17": dict(a=synth.cubic_cell(10.0), n=(24, 24, 24), nocc=17, ntgt=17, q=(0.0, 0.0, 0.0), g0=1, self=True),
+    "self_single": dict(a=synth.cubic_cell(10.0), n=(24, 24, 24), nocc=1, ntgt=1, q=(0.0, 0.0, 0.0), g0=0,
+                        self=True),
 }
 
 
