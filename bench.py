@@ -405,9 +405,13 @@ def gamma_block(name, args, cpu):
     return rec
 
 
-# Algorithmic bytes per launch of each class on full 16 x 16 tiles (units of N*b).
+# Algorithmic bytes per launch of each class on full 16 x 16 tiles (units of
+# N*b), for the k-mesh workload in FP32 (schedule 1): P3 is the in-place
+# inverse plane FFT of the tile, the second pass the streaming MAC of both
+# halves (pair buffer, both orbital tiles, both accumulator tiles read and
+# written).
 TILE_BYTES = {"p1_pair_plane_fwd": 16 + 16 + 256, "p2_pencil_energy": 256, "p2_pencil_kernel": 512,
-              "p3_plane_inv_mac": 256 + 16 + 32, "p3_second": 256 + 16 + 32}
+              "p3_plane_inv_mac": 256 + 256, "p3_second": 256 + 16 + 16 + 32 + 32}
 
 
 def kmesh_grad(name, args, cpu):

@@ -342,7 +342,9 @@ Layout layout_kmesh(long long N, int cplx_bytes, int ngroups, int nk, int nbmax)
   Layout L;
   size_t off = 0;
   L.phiA = off; off += align_up(nb * (size_t)nbmax * nk);
-  L.phiB = off; off += align_up(nb * (size_t)nbmax);
+  // gradient accumulators of every k-point: one transform per pair feeds the
+  // blocks (k, k') and (k', k)
+  L.phiB = off; off += align_up(nb * (size_t)nbmax * nk);
   L.acc = off; off += align_up(nb * (size_t)t.tj);
   L.w = off; off += align_up(nb * (size_t)t.ti * t.tj);
   L.epart = off; off += align_up(sizeof(double) * (size_t)t.ti * t.tj * ngroups);
@@ -551,6 +553,14 @@ struct Engine {
     double s0 = 0.0;
     const double* wout = nullptr;
     const double* gscale = nullptr;
+    // cross: apply only, A != B, both halves from one transform per pair: the
+    // forward half into acc_full (targets B, weights fA), the mirror half
+    // f_j psi_j conj(v_ij) into acc_mirror (the rows of A, weights fB).  Holds
+    // when the block with the roles swapped has kernel K(-q + G): its v is
+    // conj(v_ij) in real space.
+    bool cross = false;
+    void* acc_mirror = nullptr;
+    const double* fB = nullptr;
   };
 
   fock_status pairs(const KernelParams& kp, char* ws, const Layout& L, const PairJob& J, int* ntiles) {
@@ -561,6 +571,57 @@ struct Engine {
     const size_t box = (size_t)P.N * sizeof(cx<T>);
     fock_status st;
     int tile = 0;
+    if (J.cross) {
+      if (J.energy || J.sym || !J.acc_full || !J.acc_mirror || !J.fB || sym_schedule() == 0)
+        return fail(FOCK_E_ARG, "internal: bad cross-block job");
+      const int T0 = t.ti < kMacTile ? t.ti : kMacTile;
+      for (int j0 = 0; j0 < J.nB; j0 += T0) {
+        const int tj = (J.nB - j0) < T0 ? (J.nB - j0) : T0;
+        for (int i0 = 0; i0 < J.nA; i0 += T0) {
+          const int ti = (J.nA - i0) < T0 ? (J.nA - i0) : T0;
+          PlaneArgs la = plane_args(J.phiA, J.phiB, w, nullptr, J.fA, i0, j0, ti, tj);
+          if ((st = tile_forward(la, kp, false, nullptr)) != FOCK_OK) return st;
+          if (sym_schedule() == 2) {
+            PlaneArgs lp = la;
+            lp.acc = static_cast<char*>(J.acc_full) + (size_t)j0 * box;
+            {
+              FX_TRACE(KC_P3);
+              FX_HIP(launch_plane<T>(PLANE_INV_MAC, P.n[1], P.n[2], lp, tj * P.n[0], s));
+            }
+            PlaneArgs lb = la;
+            lb.f = J.fB;
+            lb.acc = static_cast<char*>(J.acc_mirror) + (size_t)i0 * box;
+            FX_TRACE(KC_P3B);
+            FX_HIP(launch_plane<T>(PLANE_INV_MAC_MIR, P.n[1], P.n[2], lb, ti * P.n[0], s));
+            continue;
+          }
+          {
+            FX_TRACE(KC_P3);
+            PlaneArgs lv = plane_args(nullptr, nullptr, nullptr, nullptr, nullptr, 0, 0, 0, 0);
+            lv.x = w;
+            lv.nb = ti * tj;
+            FX_HIP(launch_plane<T>(PLANE_INV, P.n[1], P.n[2], lv, ti * tj * P.n[0], s));
+          }
+          MacArgs ma{};
+          ma.w = w;
+          ma.phi = J.phiA;
+          ma.f = J.fA;
+          ma.acc = J.acc_mirror;
+          ma.phi_b = J.phiB;
+          ma.f_b = J.fB;
+          ma.acc_b = J.acc_full;
+          ma.N = P.N;
+          ma.i0 = i0;
+          ma.j0 = j0;
+          ma.ti = ti;
+          ma.tj = tj;
+          ma.mirror = 1;
+          FX_TRACE(KC_P3B);
+          FX_HIP(launch_mac_pair<T>(ma, s));
+        }
+      }
+      return FOCK_OK;
+    }
     if (!J.sym) {
       for (int j0 = 0; j0 < J.nB; j0 += t.tj) {
         const int tj = (J.nB - j0) < t.tj ? (J.nB - j0) : t.tj;
@@ -658,6 +719,9 @@ struct Engine {
         ma.phi = phiA;
         ma.f = J.fA;
         ma.acc = acc_all;
+        ma.phi_b = phiA;
+        ma.f_b = J.fA;
+        ma.acc_b = acc_all;
         ma.N = P.N;
         ma.i0 = i0;
         ma.j0 = j0;
@@ -991,31 +1055,59 @@ fock_status kmesh_impl(const fock_cell* cell, const Plan& P, int nk, const doubl
     FX_HIP(launch_energy_final(reinterpret_cast<double*>(ws + L.tile_e), base, scale, ex, s));
   }
   if (grad) {
-    // dE/d conj(c_jk) = w_jk sum_k' (V_x with occupied set k', q = k - k') psi_jk
-    void* acc = ws + L.phiB;
+    // dE/d conj(c_jk) = w_jk sum_k' (V_x with occupied set k', q = k - k') psi_jk.
+    // The block (k', k) has q' = -q and K(q' + G) = K(q - G), so its
+    // real-space v is conj of block (k, k')'s: every pair of a block k < k'
+    // is transformed once and feeds both gradients (schedules 1 and 2).
+    auto acc = [&](int k) { return static_cast<void*>(ws + L.phiB + (size_t)k * nbmax * box); };
     const double s0 = -1.0 / (P.omega * (double)P.N * (double)P.N);
+    const bool cross = E.sym_schedule() != 0;
     for (int k = 0; k < nk; ++k) {
       if (sets[k].nb == 0 || !grad[k]) continue;
-      {
-        FX_TRACE_S(KC_ZERO);
-        FX_HIP(launch_zero<T>(acc, P.N * sets[k].nb, s));
-      }
-      for (int kp = 0; kp < nk; ++kp) {
-        if (sets[kp].nb == 0) continue;
+      FX_TRACE_S(KC_ZERO);
+      FX_HIP(launch_zero<T>(acc(k), P.N * sets[k].nb, s));
+    }
+    auto job = [&](int kt, int ko) {
+      typename Engine<T>::PairJob J;
+      J.phiA = phi(ko);
+      J.fA = sets[ko].w;
+      J.nA = sets[ko].nb;
+      J.phiB = phi(kt);
+      J.gB = sets[kt].w;
+      J.nB = sets[kt].nb;
+      J.sym = ko == kt;
+      J.acc_full = acc(kt);
+      return J;
+    };
+    for (int k = 0; k < nk; ++k) {
+      for (int kp = k; kp < nk; ++kp) {
+        if (sets[k].nb == 0 || sets[kp].nb == 0) continue;
+        const bool gk = grad[k] != nullptr, gkp = grad[kp] != nullptr;
         double q[3];
+        if (kp == k || !cross || !(gk && gkp)) {
+          // one direction at a time: (k, kp) into k, and (kp, k) into kp
+          if (gk) {
+            const bool qz = qof(k, kp, q);
+            if ((st = E.pairs(E.kparams(q, qz, cell, d_k0), ws, L, job(k, kp), nullptr)) != FOCK_OK) return st;
+          }
+          if (kp != k && gkp) {
+            const bool qz = qof(kp, k, q);
+            if ((st = E.pairs(E.kparams(q, qz, cell, d_k0), ws, L, job(kp, k), nullptr)) != FOCK_OK) return st;
+          }
+          continue;
+        }
+        // targets at k, occupied at kp; the mirror half goes to the targets at kp
         const bool qz = qof(k, kp, q);
-        typename Engine<T>::PairJob J;
-        J.phiA = phi(kp);
-        J.fA = sets[kp].w;
-        J.nA = sets[kp].nb;
-        J.phiB = phi(k);
-        J.gB = sets[k].w;
-        J.nB = sets[k].nb;
-        J.sym = kp == k;
-        J.acc_full = acc;
+        typename Engine<T>::PairJob J = job(k, kp);
+        J.cross = true;
+        J.acc_mirror = acc(kp);
+        J.fB = sets[k].w;
         if ((st = E.pairs(E.kparams(q, qz, cell, d_k0), ws, L, J, nullptr)) != FOCK_OK) return st;
       }
-      if ((st = E.finish(acc, sets[k].nb, 0, grad[k], sets[k].ld, s0, sets[k].w, grad_ex)) != FOCK_OK) return st;
+    }
+    for (int k = 0; k < nk; ++k) {
+      if (sets[k].nb == 0 || !grad[k]) continue;
+      if ((st = E.finish(acc(k), sets[k].nb, 0, grad[k], sets[k].ld, s0, sets[k].w, grad_ex)) != FOCK_OK) return st;
     }
   }
   return FOCK_OK;

@@ -581,9 +581,12 @@ __global__ __launch_bounds__(W, MINB) void pencil_kernel(PencilArgs A) {
 // ---------------------------------------------------------------------------
 struct MacArgs {
   const void* w;       // pair buffer [ti*tj][N], slot ii*tj + jj, real space
-  const void* phi;     // orbitals in real space [n][N]
-  const double* f;     // occupations
-  void* acc;           // accumulators [n][N]
+  const void* phi;     // occupied orbitals (set A) in real space [n][N]
+  const double* f;     // occupations of set A
+  void* acc;           // accumulators of set A [n][N] (mirror half)
+  const void* phi_b;   // target orbitals (set B) and their weights / accumulators
+  const double* f_b;   //   (forward half); all three equal the set-A ones when
+  void* acc_b;         //   one block is applied to itself
   long long N;
   int i0, j0, ti, tj, mirror;
   int tri;             // diagonal tile: pairs ii <= jj at tri_slot(ii, jj); forward ii <= jj, mirror ii < jj
@@ -598,8 +601,13 @@ __global__ __launch_bounds__(256) void mac_pair_kernel(MacArgs A) {
   if (p >= N) return;
   const cx<T>* __restrict__ w = reinterpret_cast<const cx<T>*>(A.w) + p;
   const cx<T>* __restrict__ phi = reinterpret_cast<const cx<T>*>(A.phi) + p;
-  cx<T>* __restrict__ acc = reinterpret_cast<cx<T>*>(A.acc) + p;
+  // acc and acc_b are the same array when a block is applied to itself (on a
+  // diagonal tile even the same rows): no __restrict__ on either
+  cx<T>* acc = reinterpret_cast<cx<T>*>(A.acc) + p;
   const double* __restrict__ f = A.f;
+  const cx<T>* __restrict__ phi_b = reinterpret_cast<const cx<T>*>(A.phi_b) + p;
+  cx<T>* acc_b = reinterpret_cast<cx<T>*>(A.acc_b) + p;
+  const double* __restrict__ f_b = A.f_b;
   const int ti = A.ti, tj = A.tj, mirror = A.mirror, tri = A.tri;
   cx<T> fphi_i[kMacTile], acc_i[kMacTile];
 #pragma unroll
@@ -609,8 +617,8 @@ __global__ __launch_bounds__(256) void mac_pair_kernel(MacArgs A) {
   }
   for (int jj = 0; jj < tj; ++jj) {
     const long long oj = (long long)(A.j0 + jj) * N;
-    const cx<T> aj0 = acc[oj];
-    const cx<T> fphi_j = cscale<T>(phi[oj], T(f[A.j0 + jj]));
+    const cx<T> aj0 = acc_b[oj];
+    const cx<T> fphi_j = cscale<T>(phi_b[oj], T(f_b[A.j0 + jj]));
     const int iend = tri ? jj + 1 : ti;  // forward: ii < iend; mirror: ii < jj on a diagonal tile
     cx<T> v[kMacTile];
 #pragma unroll
@@ -629,7 +637,7 @@ __global__ __launch_bounds__(256) void mac_pair_kernel(MacArgs A) {
         }
       }
     }
-    acc[oj] = mk<T>(sx, sy);
+    acc_b[oj] = mk<T>(sx, sy);
   }
   if (mirror) {
 #pragma unroll

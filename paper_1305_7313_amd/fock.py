@@ -404,10 +404,11 @@ def fock_energy_kmesh(cell: Cell, kpts, C, W, out=None, ws=None):
 
 
 def fock_energy_kmesh_backward(cell: Cell, kpts, C, W, grad_ex, grad, ws=None):
-    """grad[k] = grad_ex * dE/dconj(C[k]) (C call: fock_energy_kmesh_backward)."""
+    """grad[k] = grad_ex * dE/dconj(C[k]) (C call: fock_energy_kmesh_backward);
+    a None entry skips that k-point."""
     dt = dtype_code(C)
     nk, kp, sets = _kmesh_args(kpts, C, W)
-    ptrs = (ctypes.c_void_p * nk)(*[grad[k].data_ptr() for k in range(nk)])
+    ptrs = (ctypes.c_void_p * nk)(*[grad[k].data_ptr() if grad[k] is not None else None for k in range(nk)])
     if ws is None:
         ws = workspace_kmesh(cell, dt, nk, int(C.shape[1]), C.device)
     _check(lib().fock_energy_kmesh_backward(ctypes.byref(cell.c), nk,

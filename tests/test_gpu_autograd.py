@@ -135,3 +135,57 @@ def test_kmesh_gaussian_closed_form():
     ref = -1.0 / (2 * sigma * np.sqrt(np.pi))
     report("kmesh Gaussian closed form", E=e, ref=ref, rel=abs(e - ref) / abs(ref))
     assert abs(e - ref) < 1e-11 * abs(ref)
+
+
+@pytest.fixture(scope="module")
+def kmesh17():
+    """2x2x2 mesh, 17 orbitals per k (pair tiles of 16 and 1), random
+    weights; the oracle gradient on rows 0 and 16 of every k-point, as
+    w_jk sum_k' (V_x with occupied set k', q = k - k') psi_jk."""
+    s = synth.make_system(synth.cubic_cell(8.0), (24, 24, 24))
+    nq = (2, 2, 2)
+    kpts = synth.kmesh_points(s.a, nq)
+    sets = [synth.random_orbitals(s.a, s.miller, 17, 50 + k) for k in range(8)]
+    w = [np.random.default_rng(60 + k).uniform(0.05, 0.2, 17) for k in range(8)]
+    alpha = 10.0 / s.ecut
+    k0 = exx.gb_constant(s.a, s.n, nq, alpha)
+    rows = [0, 16]
+    g = []
+    for k in range(8):
+        acc = 0.0
+        for kp in range(8):
+            q = np.asarray(kpts[k]) - np.asarray(kpts[kp])
+            acc = acc + exx.fock_apply(s.a, s.n, s.miller, q, sets[kp], w[kp], sets[k][rows], k0=k0)
+        g.append(w[k][rows][:, None] * acc)
+    return s, nq, kpts, sets, w, alpha, rows, g
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+@pytest.mark.parametrize("schedule", ["0", "1", "2"])
+def test_kmesh_gradient_cross_blocks(kmesh17, prec, schedule, monkeypatch):
+    """Schedules 1 and 2 transform each pair of the blocks k < k' once and
+    apply it to both k-points' gradients (the block (k', k) has conj(v) in
+    real space); schedule 0 runs every block separately.  Also: gradients
+    requested for the even k-points only."""
+    import torch
+    F, _ = _mods()
+    s, nq, kpts, sets, w, alpha, rows, g_ref = kmesh17
+    monkeypatch.setenv("FOCK_SYM_SCHEDULE", schedule)
+    cdt = torch.complex128 if prec == "c128" else torch.complex64
+    tol = 1e-10 if prec == "c128" else 1e-5
+    cell = _gb_cell(F, s, nq, alpha)
+    C = torch.from_numpy(np.stack(sets)).to(cdt).cuda()
+    W = torch.from_numpy(np.stack(w)).cuda()
+    one = torch.ones((), dtype=torch.float64, device="cuda")
+    print(f"[case] kmesh 17 orbitals {prec} schedule={schedule}", flush=True)
+    G = torch.empty_like(C)
+    F.fock_energy_kmesh_backward(cell, kpts, C, W, one, [G[k] for k in range(8)])
+    Gh = host(G)
+    H = torch.full_like(C, float("nan"))
+    F.fock_energy_kmesh_backward(cell, kpts, C, W, one, [H[k] if k % 2 == 0 else None for k in range(8)])
+    Hh = host(H)
+    err = max(rel_fro(Gh[k][rows], g_ref[k]) for k in range(8))
+    err_even = max(rel_fro(Hh[k][rows], g_ref[k]) for k in range(0, 8, 2))
+    untouched = all(np.isnan(Hh[k]).all() for k in range(1, 8, 2))
+    report(f"kmesh 17 {prec} schedule={schedule}", grad_rel=err, even_only_rel=err_even)
+    assert err < tol and err_even < tol and untouched
