@@ -433,12 +433,10 @@ def kmesh_grad(name, args, cpu):
     W = torch.full((nk, nb), 1.0 / nk, dtype=torch.float64, device="cuda")
     ws = fock.workspace_kmesh(cell, fock.FOCK_C64, nk, nb, C.device)
     ex = torch.empty((), dtype=torch.float64, device="cuda")
-    one = torch.ones((), dtype=torch.float64, device="cuda")
     G = torch.empty_like(C)
 
     def step():
-        fock.fock_energy_kmesh(cell, kpts, C, W, out=ex, ws=ws)
-        fock.fock_energy_kmesh_backward(cell, kpts, C, W, one, [G[k] for k in range(nk)], ws=ws)
+        fock.fock_energy_kmesh_grad(cell, kpts, C, W, grad=G, out=ex, ws=ws)
 
     # one step takes tens of seconds: at most 2 timed steps after 1 warmup
     steps, warmup = min(args.steps, 2), min(args.warmup, 1)
@@ -448,7 +446,9 @@ def kmesh_grad(name, args, cpu):
            "warmup": warmup,
            "config": {"workload": name, "description": WORKLOADS[name], "grid": list(n), "npw": s.npw,
                       "ecut_fock": ecut if ecut > 0.0 else None, "kpoints": nk, "bands_per_k": nb, "pairs_per_step": pairs,
-                      "step": "E_x over the mesh (blocks k <= k' only, E_kk' = E_k'k) and dE/dconj(C)"},
+                      "step": "E_x over the mesh and dE/dconj(C) from one pass over the pairs "
+                              "(fock_energy_kmesh_grad: each pair of the blocks k < k' transformed once for "
+                              "both gradients, E = 1/2 Re <C, dE/dconj(C)>)"},
            "cpu_baseline": cpu or None}
     if not args.no_trace:
         tr = traced(fock, step, 1)

@@ -142,6 +142,15 @@ fock_status fock_energy_kmesh(const fock_cell *cell, int32_t nk, const double *k
 fock_status fock_energy_kmesh_backward(const fock_cell *cell, int32_t nk, const double *kpts, int32_t dtype,
                                        const fock_orbs *sets, const double *grad_ex, void *const *grad, void *ws,
                                        size_t ws_bytes, void *stream);
+/* Energy and gradient of fock_energy_kmesh together, from one pass over the
+ * pairs: grad[k][j] = dE/d conj(c_jk) (unscaled; every entry of grad with
+ * sets[k].nb > 0 must be non-NULL), then *ex_out = 1/2 Re sum_k sum_j
+ * sum_p conj(c_jk[p]) grad[k][j][p].  E has degree 2 in the conjugated
+ * coefficients, so this equals fock_energy_kmesh up to rounding (the
+ * energy pass is not run).  Same workspace as fock_energy_kmesh. */
+fock_status fock_energy_kmesh_grad(const fock_cell *cell, int32_t nk, const double *kpts, int32_t dtype,
+                                   const fock_orbs *sets, double *ex_out, void *const *grad, void *ws,
+                                   size_t ws_bytes, void *stream);
 
 /* Batched form: several independent systems, each an apply as fock_apply
  * (occupied block occ[s], target block tgt[s], q[s]) on its own cell and

@@ -339,6 +339,8 @@ Layout layout_kmesh(long long N, int cplx_bytes, int ngroups, int nk, int nbmax)
   const size_t nb = (size_t)N * cplx_bytes;
   const int ntb = (nbmax + t.ti - 1) / t.ti;
   const int ntiles = (nk * (nk + 1) / 2) * (ntb > 0 ? ntb * ntb : 1);
+  // tile_e also holds the per-band partials of the energy taken from the gradient
+  const int nparts = ntiles > nk * nbmax ? ntiles : nk * nbmax;
   Layout L;
   size_t off = 0;
   L.phiA = off; off += align_up(nb * (size_t)nbmax * nk);
@@ -348,7 +350,7 @@ Layout layout_kmesh(long long N, int cplx_bytes, int ngroups, int nk, int nbmax)
   L.acc = off; off += align_up(nb * (size_t)t.tj);
   L.w = off; off += align_up(nb * (size_t)t.ti * t.tj);
   L.epart = off; off += align_up(sizeof(double) * (size_t)t.ti * t.tj * ngroups);
-  L.tile_e = off; off += align_up(sizeof(double) * (size_t)ntiles);
+  L.tile_e = off; off += align_up(sizeof(double) * (size_t)nparts);
   L.k0 = off; off += align_up(sizeof(double));
   L.gbpart = off; off += align_up(sizeof(double) * kGbParts);
   L.total = off;
@@ -1009,10 +1011,12 @@ fock_status prepare(const fock_cell* cell, const double q[3], int dtype, const f
 
 // Exchange energy over a k-point mesh and its gradient.  Block (k, k')
 // pairs targets at k with occupied orbitals at k', q = k - k'.
+// ex_from_grad (with ex and grad, grad_ex null): no energy pass; after the
+// gradient, E = 1/2 Re sum_k sum_j <c_jk | dE/d conj(c_jk)>.
 template <typename T>
 fock_status kmesh_impl(const fock_cell* cell, const Plan& P, int nk, const double* kpts, const fock_orbs* sets,
                        char* ws, const Layout& L, hipStream_t s, double* ex, const double* grad_ex,
-                       void* const* grad) {
+                       void* const* grad, bool ex_from_grad = false) {
   Engine<T> E(P, s);
   const size_t box = (size_t)P.N * sizeof(cx<T>);
   int nbmax = 0;
@@ -1027,7 +1031,7 @@ fock_status kmesh_impl(const fock_cell* cell, const Plan& P, int nk, const doubl
     for (int a = 0; a < 3; ++a) q[a] = kpts[3 * kt + a] - kpts[3 * ko + a];
     return q[0] == 0.0 && q[1] == 0.0 && q[2] == 0.0;
   };
-  if (ex) {
+  if (ex && !ex_from_grad) {
     // E_kk' = E_k'k: blocks k <= k' only, off-diagonal ones counted twice
     int base = 0;
     for (int k = 0; k < nk; ++k) {
@@ -1108,6 +1112,21 @@ fock_status kmesh_impl(const fock_cell* cell, const Plan& P, int nk, const doubl
     for (int k = 0; k < nk; ++k) {
       if (sets[k].nb == 0 || !grad[k]) continue;
       if ((st = E.finish(acc(k), sets[k].nb, 0, grad[k], sets[k].ld, s0, sets[k].w, grad_ex)) != FOCK_OK) return st;
+    }
+  }
+  if (ex && ex_from_grad) {
+    double* part = reinterpret_cast<double*>(ws + L.tile_e);
+    int off = 0;
+    for (int k = 0; k < nk; ++k) {
+      if (sets[k].nb == 0) continue;
+      FX_TRACE(KC_REDUCE);
+      FX_HIP(launch_band_dot<T>(sets[k].c, sets[k].ld, grad[k], sets[k].ld, P.npw, nullptr, sets[k].nb, part + off, s));
+      off += sets[k].nb;
+    }
+    if (off == 0) {
+      FX_HIP(launch_set_scalar(ex, 0.0, s));
+    } else {
+      FX_HIP(launch_energy_final(part, off, 0.5, ex, s));
     }
   }
   return FOCK_OK;
@@ -1950,6 +1969,23 @@ fock_status fock_energy_kmesh_backward(const fock_cell* cell, int32_t nk, const 
   char* w = static_cast<char*>(ws);
   if (dtype == FOCK_C128) return kmesh_impl<double>(cell, *plan, nk, kpts, sets, w, L, s, nullptr, grad_ex, grad);
   return kmesh_impl<float>(cell, *plan, nk, kpts, sets, w, L, s, nullptr, grad_ex, grad);
+}
+
+fock_status fock_energy_kmesh_grad(const fock_cell* cell, int32_t nk, const double* kpts, int32_t dtype,
+                                   const fock_orbs* sets, double* ex_out, void* const* grad, void* ws,
+                                   size_t ws_bytes, void* stream) {
+  if (!ex_out || !grad) return fail(FOCK_E_ARG, "ex_out and grad must not be NULL");
+  if (sets && nk > 0)
+    for (int k = 0; k < nk; ++k)
+      if (sets[k].nb > 0 && !grad[k]) return fail(FOCK_E_ARG, "grad[" + std::to_string(k) + "] is NULL");
+  std::shared_ptr<Plan> plan;
+  Layout L;
+  fock_status st = kmesh_prepare(cell, nk, kpts, dtype, sets, ws, ws_bytes, &plan, &L);
+  if (st != FOCK_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  char* w = static_cast<char*>(ws);
+  if (dtype == FOCK_C128) return kmesh_impl<double>(cell, *plan, nk, kpts, sets, w, L, s, ex_out, nullptr, grad, true);
+  return kmesh_impl<float>(cell, *plan, nk, kpts, sets, w, L, s, ex_out, nullptr, grad, true);
 }
 
 fock_status fock_fft3d(const int32_t n[3], int32_t dtype, int32_t sign, void* x, int32_t nb, void* stream) {

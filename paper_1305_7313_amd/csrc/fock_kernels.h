@@ -808,8 +808,10 @@ __global__ void gather_unpack_kernel(const cx<T>* __restrict__ box, long long N,
   }
 }
 
-// part[b] = g[b] Re sum_p conj(c[b][p]) v[b][p]  (one block per band, FP64 sum):
-// with v = V_x psi, 1/2 sum_b part[b] is the exchange energy of the block.
+// part[b] = g[b] Re sum_p conj(c[b][p]) v[b][p]  (one block per band, FP64 sum;
+// g null: weight 1).  With v = V_x psi, 1/2 sum_b part[b] is the exchange
+// energy of the block; with v = dE/d conj(c) (weights already inside),
+// 1/2 sum_b part[b] is E itself (E has degree 2 in conj(c)).
 template <typename T>
 __global__ void band_dot_kernel(const cx<T>* __restrict__ c, int ldc, const cx<T>* __restrict__ v, int ldv, int npw,
                                 const double* __restrict__ g, double* __restrict__ part) {
@@ -823,7 +825,7 @@ __global__ void band_dot_kernel(const cx<T>* __restrict__ c, int ldc, const cx<T
     s += double(x.x) * double(y.x) + double(x.y) * double(y.y);
   }
   const double tot = block_sum(s, red);
-  if (threadIdx.x == 0) part[b] = g[b] * tot;
+  if (threadIdx.x == 0) part[b] = g ? g[b] * tot : tot;
 }
 
 // Band force on the sphere:

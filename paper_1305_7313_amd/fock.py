@@ -85,6 +85,10 @@ def lib():
         L.fock_energy_kmesh_backward.argtypes = [P(fock_cell), ctypes.c_int32, P(ctypes.c_double), ctypes.c_int32,
                                                  P(fock_orbs), ctypes.c_void_p, P(ctypes.c_void_p),
                                                  ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
+        L.fock_energy_kmesh_grad.restype = ctypes.c_int
+        L.fock_energy_kmesh_grad.argtypes = [P(fock_cell), ctypes.c_int32, P(ctypes.c_double), ctypes.c_int32,
+                                             P(fock_orbs), ctypes.c_void_p, P(ctypes.c_void_p), ctypes.c_void_p,
+                                             ctypes.c_size_t, ctypes.c_void_p]
         L.fock_batch_plan_create.restype = ctypes.c_int
         L.fock_batch_plan_create.argtypes = [P(fock_cell), P(fock_orbs), P(fock_orbs), P(ctypes.c_double * 3),
                                              ctypes.c_int32, ctypes.c_int32, ctypes.c_char_p, P(ctypes.c_void_p)]
@@ -416,6 +420,25 @@ def fock_energy_kmesh_backward(cell: Cell, kpts, C, W, grad_ex, grad, ws=None):
                                             grad_ex.data_ptr(), ptrs, ws.data_ptr(), ws.numel(),
                                             _stream(C.device)))
     return grad
+
+
+def fock_energy_kmesh_grad(cell: Cell, kpts, C, W, grad=None, out=None, ws=None):
+    """E and grad[k] = dE/dconj(C[k]) from one pass (C call:
+    fock_energy_kmesh_grad).  Returns (E as a device FP64 scalar, grad)."""
+    import torch
+    dt = dtype_code(C)
+    nk, kp, sets = _kmesh_args(kpts, C, W)
+    if grad is None:
+        grad = torch.empty_like(C)
+    if out is None:
+        out = torch.empty((), dtype=torch.float64, device=C.device)
+    ptrs = (ctypes.c_void_p * nk)(*[grad[k].data_ptr() for k in range(nk)])
+    if ws is None:
+        ws = workspace_kmesh(cell, dt, nk, int(C.shape[1]), C.device)
+    _check(lib().fock_energy_kmesh_grad(ctypes.byref(cell.c), nk,
+                                        kp.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), dt, sets,
+                                        out.data_ptr(), ptrs, ws.data_ptr(), ws.numel(), _stream(C.device)))
+    return out, grad
 
 
 # ---------------------------------------------------------------------------

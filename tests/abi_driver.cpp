@@ -97,6 +97,11 @@ int main() {
   void* grads[2] = {out, out};
   EXPECT(reached_device_or_ok(
       fock_energy_kmesh_backward(&cell, 2, kpts, FOCK_C64, sets, ex, grads, ws, big, nullptr)));
+  EXPECT(fock_energy_kmesh_grad(&cell, 2, kpts, FOCK_C64, sets, nullptr, grads, ws, big, nullptr) == FOCK_E_ARG);
+  void* half[2] = {out, nullptr};
+  EXPECT(fock_energy_kmesh_grad(&cell, 2, kpts, FOCK_C64, sets, ex, half, ws, big, nullptr) == FOCK_E_ARG);
+  EXPECT(fock_energy_kmesh_grad(&cell, 2, kpts, FOCK_C64, sets, ex, grads, ws, 64, nullptr) == FOCK_E_WORKSPACE);
+  EXPECT(reached_device_or_ok(fock_energy_kmesh_grad(&cell, 2, kpts, FOCK_C64, sets, ex, grads, ws, big, nullptr)));
   EXPECT(fock_apply_gamma(&cell, FOCK_C128, &o, out, ws, 8, nullptr) == FOCK_E_WORKSPACE);
   EXPECT(reached_device_or_ok(fock_apply_gamma(&cell, FOCK_C128, &o, out, ws, big, nullptr)));
   EXPECT(fock_band_density(&cell, FOCK_C128, &o, nullptr, ws, big, nullptr) != FOCK_OK);

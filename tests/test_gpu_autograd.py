@@ -189,3 +189,35 @@ def test_kmesh_gradient_cross_blocks(kmesh17, prec, schedule, monkeypatch):
     untouched = all(np.isnan(Hh[k]).all() for k in range(1, 8, 2))
     report(f"kmesh 17 {prec} schedule={schedule}", grad_rel=err, even_only_rel=err_even)
     assert err < tol and err_even < tol and untouched
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_kmesh_energy_and_grad_in_one_pass(reduced, kmesh17, prec):
+    """fock_energy_kmesh_grad: the gradient sweep alone, E = 1/2 Re <C, dE/dconj C>.
+    Against the oracle on the reduced instance; against the separate energy
+    and backward calls on the 17-orbital mesh (gradient bit for bit)."""
+    import torch
+    F, _ = _mods()
+    cdt = torch.complex128 if prec == "c128" else torch.complex64
+    tol = 1e-10 if prec == "c128" else 1e-5
+    one = torch.ones((), dtype=torch.float64, device="cuda")
+    s, nq, kpts, sets, w, alpha, e_ref, g_ref = reduced
+    cell = _gb_cell(F, s, nq, alpha)
+    C = torch.from_numpy(np.stack(sets)).to(cdt).cuda()
+    W = torch.from_numpy(np.stack(w)).cuda()
+    print(f"[case] kmesh energy+grad one pass {prec}", flush=True)
+    e, G = F.fock_energy_kmesh_grad(cell, kpts, C, W)
+    err_e = abs(float(host(e)) - e_ref) / abs(e_ref)
+    err_g = rel_fro(host(G), np.stack(g_ref))
+    s, nq, kpts, sets, w, alpha, rows, _ = kmesh17
+    cell = _gb_cell(F, s, nq, alpha)
+    C = torch.from_numpy(np.stack(sets)).to(cdt).cuda()
+    W = torch.from_numpy(np.stack(w)).cuda()
+    e1, G1 = F.fock_energy_kmesh_grad(cell, kpts, C, W)
+    e2 = float(host(F.fock_energy_kmesh(cell, kpts, C, W)))
+    G2 = torch.empty_like(C)
+    F.fock_energy_kmesh_backward(cell, kpts, C, W, one, [G2[k] for k in range(8)])
+    err_e17 = abs(float(host(e1)) - e2) / abs(e2)
+    same = np.array_equal(host(G1), host(G2))
+    report(f"kmesh one pass {prec}", E_rel=err_e, grad_rel=err_g, E_vs_energy_pass=err_e17, grad_bitwise=same)
+    assert err_e < tol and err_g < tol and err_e17 < tol and same
