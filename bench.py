@@ -218,10 +218,12 @@ def gamma_step_bytes(n, N, bpc, ti_max=16, tj_max=8):
                 break
             ti = min(ti_max, n - i0)
             pi = (ti + 1) // 2  # packed planes holding the tile's occupied orbitals
-            add("p1_pair_plane_fwd", pi + tj, ti * tj)
-            add("p2_pencil_kernel", ti * tj, ti * tj)
-            add("p3_plane_inv_mac", ti * tj + pi + tj, tj)
-            add("p3_second", ti * tj + tj + pi, pi)
+            # diagonal tile: only the pairs i <= 2q + 1 (non-zero weight)
+            npr = sum(min(ti, 2 * jj + 2) for jj in range(tj)) if i0 == 2 * j0 else ti * tj
+            add("p1_pair_plane_fwd", pi + tj, npr)
+            add("p2_pencil_kernel", npr, npr)
+            add("p3_plane_inv_mac", npr + pi + tj, tj)
+            add("p3_second", npr + tj + pi, pi)
     return acc
 
 

@@ -465,7 +465,7 @@ struct Engine {
   // P1 and P2 of one pair tile (energy: P2 only accumulates partials).
   fock_status tile_forward(const PlaneArgs& la, const KernelParams& kp, bool energy, double* epart,
                            int p1_mode = PLANE_PAIR_FWD) {
-    const int tt = la.tri ? tri_slot(0, la.ti) : la.ti * la.tj;
+    const int tt = !la.tri ? la.ti * la.tj : p1_mode == PLANE_PAIR_FWD_G ? gtri_prefix(la.ti, la.tj) : tri_slot(0, la.ti);
     {
       FX_TRACE(KC_P1);
       FX_HIP(launch_plane<T>(p1_mode, P.n[1], P.n[2], la, tt * P.n[0], s));
@@ -824,14 +824,18 @@ fock_status apply_gamma_impl(const fock_cell* cell, const Plan& P, const fock_or
       const int ti = std::min(kGammaTi, n - i0);
       PlaneArgs la = E.plane_args(pk, pk, ws + L.w, nullptr, o->w, i0, j0, ti, tj);
       la.nreal = n;
+      // diagonal tile (the occupied reals of the packed targets): only the
+      // pairs with a non-zero weight, i <= 2q + 1, are transformed
+      la.tri = i0 == 2 * j0;
+      const int tt = la.tri ? gtri_prefix(ti, tj) : ti * tj;
       if ((st = E.tile_forward(la, kp, false, nullptr, PLANE_PAIR_FWD_G)) != FOCK_OK) return st;
       if (E.gamma_schedule() == 1) {
         {
           FX_TRACE(KC_P3);
           PlaneArgs lv = E.plane_args(nullptr, nullptr, nullptr, nullptr, nullptr, 0, 0, 0, 0);
           lv.x = ws + L.w;
-          lv.nb = ti * tj;
-          FX_HIP(launch_plane<T>(PLANE_INV, P.n[1], P.n[2], lv, ti * tj * P.n[0], s));
+          lv.nb = tt;
+          FX_HIP(launch_plane<T>(PLANE_INV, P.n[1], P.n[2], lv, tt * P.n[0], s));
         }
         MacArgs ma{};
         ma.w = ws + L.w;
@@ -843,6 +847,7 @@ fock_status apply_gamma_impl(const fock_cell* cell, const Plan& P, const fock_or
         ma.j0 = j0;
         ma.ti = ti;
         ma.tj = tj;
+        ma.tri = la.tri;
         FX_TRACE(KC_P3B);
         FX_HIP(launch_mac_gamma<T>(ma, n, s));
         continue;

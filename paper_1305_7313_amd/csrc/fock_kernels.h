@@ -81,6 +81,16 @@ struct PlaneArgs {
 // Slot of pair (ii, jj), ii <= jj, in the pair buffer of a diagonal tile.
 __host__ __device__ constexpr int tri_slot(int ii, int jj) { return jj * (jj + 1) / 2 + ii; }
 
+// Gamma diagonal tile (real occupied i0 = 2 j0): packed target jj needs the
+// occupied ii < gtri_count(ti, jj) (i <= 2q + 1; the rest have zero weights),
+// stored from slot gtri_prefix(ti, jj).
+__host__ __device__ constexpr int gtri_count(int ti, int jj) { return ti < 2 * jj + 2 ? ti : 2 * jj + 2; }
+__host__ __device__ constexpr int gtri_prefix(int ti, int jj) {
+  int s = 0;
+  for (int j = 0; j < jj; ++j) s += gtri_count(ti, j);
+  return s;
+}
+
 struct PencilArgs {
   void* x;             // [npairs or nb][N]
   double* epart;       // energy partials [ngroups][npairs] (group-major) or null
@@ -153,11 +163,18 @@ __device__ __forceinline__ void plane_body(const PlaneArgs& A, int lid, unsigned
   cx<T> v[Cfg::NV];
 
   if constexpr (MODE == PLANE_PAIR_FWD || MODE == PLANE_PAIR_FWD_G) {
-    // workgroup (i1, slot): slot = ii * tj + jj, or tri_slot(ii, jj) on a diagonal tile
-    const int tt = A.tri ? A.ti * (A.ti + 1) / 2 : A.ti * A.tj;
+    // workgroup (i1, slot): slot = ii * tj + jj, or on a diagonal tile
+    // tri_slot(ii, jj) (gtri_prefix(ti, jj) + ii in the Gamma modes)
+    constexpr bool gam = MODE == PLANE_PAIR_FWD_G;
+    const int tt = A.tri ? (gam ? gtri_prefix(A.ti, A.tj) : A.ti * (A.ti + 1) / 2) : A.ti * A.tj;
     const int i1 = lid / tt, rem = lid - i1 * tt;
     int ii, jj;
-    if (A.tri) {
+    if (A.tri && gam) {
+      jj = 0;
+      int base = 0;
+      while (rem >= base + gtri_count(A.ti, jj)) base += gtri_count(A.ti, jj++);
+      ii = rem - base;
+    } else if (A.tri) {
       jj = 0;
       while (tri_slot(0, jj + 1) <= rem) ++jj;
       ii = rem - tri_slot(0, jj);
@@ -250,17 +267,24 @@ __device__ __forceinline__ void plane_body(const PlaneArgs& A, int lid, unsigned
     // PLANE_INV_MAC_G: block (jj, i1), loop over ii, into packed acc_q.
     // PLANE_INV_MAC_MIR_G: block (ii, i1), loop over jj, into component
     // (i & 1) of packed acc_{i/2} (acc points at the tile's first pair).
+    // On a diagonal tile (tri) only the stored pairs ii < gtri_count(ti, jj) are visited.
     constexpr bool mir = MODE == PLANE_INV_MAC_MIR_G;
     const int nblk = mir ? A.ti : A.tj, nloop = mir ? A.tj : A.ti;
     const int i1 = lid / nblk, bi = lid - (lid / nblk) * nblk;
+    int k0 = 0, k1 = nloop;
+    if (A.tri) {
+      if (mir) k0 = bi / 2;  // first jj with bi < 2 jj + 2
+      else k1 = gtri_count(A.ti, bi);
+    }
     cx<T> s[R1::NV];
 #pragma unroll
     for (int e = 0; e < R1::NV; ++e) s[e] = mk<T>(T(0), T(0));
-    for (int k = 0; k < nloop; ++k) {
+    for (int k = k0; k < k1; ++k) {
       const int ii = mir ? bi : k, jj = mir ? k : bi;
       const int i = A.i0 + ii, q = A.j0 + jj;
       const int j0r = 2 * q, j1r = 2 * q + 1;
-      const cx<T>* pw = reinterpret_cast<const cx<T>*>(A.w) + (long long)(ii * A.tj + jj) * N + (long long)i1 * PLANE;
+      const int slot = A.tri ? gtri_prefix(A.ti, jj) + ii : ii * A.tj + jj;
+      const cx<T>* pw = reinterpret_cast<const cx<T>*>(A.w) + (long long)slot * N + (long long)i1 * PLANE;
       for_inputs<C0>(t, [&](int e, int row, int col) { v[e] = pw[row * N3 + col]; });
       pass_compute<C0, +1, T>(v, tw2, t);
       exchange<C0, C1, N3, SPLIT, T, PAD>(v, smem, t);
@@ -685,12 +709,16 @@ __global__ __launch_bounds__(256) void mac_gamma_kernel(MacArgs A, int nreal) {
     const cx<T> P = pk[oq];
     const cx<T> a0 = acc[oq];
     const T fj0 = T(f[j0r]), fj1 = two ? T(f[j1r]) : T(0);
+    // diagonal tile: only ii < gtri_count(ti, jj) is stored, from gtri_prefix(ti, jj)
+    const int iend = A.tri ? gtri_count(ti, jj) : ti;
+    const int base = A.tri ? gtri_prefix(ti, jj) : jj;
+    const int stride = A.tri ? 1 : tj;
     T sx = a0.x, sy = a0.y;
 #pragma unroll
     for (int ii = 0; ii < kMacTile; ++ii) {
-      if (ii < ti) {
+      if (ii < iend) {
         const int i = A.i0 + ii;
-        const cx<T> v = w[(long long)(ii * tj + jj) * N];
+        const cx<T> v = w[(long long)(base + ii * stride) * N];
         const T fi = T(f[i]);
         const T w0 = i <= j0r ? fi : T(0), w1 = (i <= j1r && two) ? fi : T(0);
         sx += w0 * phi_i[ii] * v.x;
