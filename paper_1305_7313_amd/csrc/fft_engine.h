@@ -37,6 +37,14 @@ template <> struct cx_of<float> { using type = float2; };
 template <> struct cx_of<double> { using type = double2; };
 template <typename T> using cx = typename cx_of<T>::type;
 
+// Store marked non-temporal, for a pair buffer written in full by one pass
+// and read once by the next: the lines need not stay in the caches.
+template <typename T> __device__ __forceinline__ void store_stream(cx<T>* p, cx<T> v) {
+  using V = T __attribute__((ext_vector_type(2)));
+  V x = {v.x, v.y};
+  __builtin_nontemporal_store(x, reinterpret_cast<V*>(p));
+}
+
 template <typename T> __host__ __device__ __forceinline__ cx<T> mk(T x, T y) {
   cx<T> r;
   r.x = x;

@@ -208,7 +208,7 @@ __device__ __forceinline__ void plane_body(const PlaneArgs& A, int lid, unsigned
     exchange<C0, C1, N3, SPLIT, T, PAD>(v, smem, t);
     pass_compute<C1, -1, T>(v, tw2, t);
     cx<T>* pw = reinterpret_cast<cx<T>*>(A.w) + (long long)rem * N + (long long)i1 * PLANE;
-    for_outputs<C1>(t, [&](int e, int row, int col) { pw[row * N3 + col] = v[e]; });
+    for_outputs<C1>(t, [&](int e, int row, int col) { store_stream<T>(&pw[row * N3 + col], v[e]); });
   } else if constexpr (MODE == PLANE_INV_MAC || MODE == PLANE_INV_MAC_MIR) {
     // PLANE_INV_MAC: block (jj, i1), loop over ii, acc_j += f_i phi_i v_ij.
     // PLANE_INV_MAC_MIR (one orbital block at q = 0): block (ii, i1), loop over
@@ -572,7 +572,7 @@ __device__ __forceinline__ void pencil_body(const PencilArgs& A, int lid, unsign
       pass_compute<P0, +1, T>(v, tw1, t);
       exchange<P0, P1, CB, SPLIT, T>(v, smem, t);
       pass_compute<P1, +1, T>(v, tw1, t);
-      for_outputs<P1>(t, [&](int e, int row, int col) { base[(long long)row * plane + col] = v[e]; });
+      for_outputs<P1>(t, [&](int e, int row, int col) { store_stream<T>(&base[(long long)row * plane + col], v[e]); });
     }
   }
 }
