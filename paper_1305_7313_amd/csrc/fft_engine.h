@@ -37,8 +37,17 @@ template <> struct cx_of<float> { using type = float2; };
 template <> struct cx_of<double> { using type = double2; };
 template <typename T> using cx = typename cx_of<T>::type;
 
-// Store marked non-temporal, for a pair buffer written in full by one pass
-// and read once by the next: the lines need not stay in the caches.
+// Load and store marked non-temporal, for the pair buffer: each pass writes
+// a tile's pairs in full or reads each of them once, so its lines need not
+// stay in the caches, which then keep the orbital planes the passes re-read.
+template <typename T> __device__ __forceinline__ cx<T> load_stream(const cx<T>* p) {
+  using V = T __attribute__((ext_vector_type(2)));
+  const V x = __builtin_nontemporal_load(reinterpret_cast<const V*>(p));
+  cx<T> r;
+  r.x = x.x;
+  r.y = x.y;
+  return r;
+}
 template <typename T> __device__ __forceinline__ void store_stream(cx<T>* p, cx<T> v) {
   using V = T __attribute__((ext_vector_type(2)));
   V x = {v.x, v.y};

@@ -227,7 +227,7 @@ __device__ __forceinline__ void plane_body(const PlaneArgs& A, int lid, unsigned
     for (int k = k0; k < k1; ++k) {
       const int slot = A.tri ? (mir ? tri_slot(bi, k) : tri_slot(k, bi)) : (mir ? bi * A.tj + k : k * A.tj + bi);
       const cx<T>* pw = reinterpret_cast<const cx<T>*>(A.w) + (long long)slot * N + (long long)i1 * PLANE;
-      for_inputs<C0>(t, [&](int e, int row, int col) { v[e] = pw[row * N3 + col]; });
+      for_inputs<C0>(t, [&](int e, int row, int col) { v[e] = load_stream<T>(&pw[row * N3 + col]); });
       pass_compute<C0, +1, T>(v, tw2, t);
       exchange<C0, C1, N3, SPLIT, T, PAD>(v, smem, t);
       pass_compute<C1, +1, T>(v, tw2, t);
@@ -285,7 +285,7 @@ __device__ __forceinline__ void plane_body(const PlaneArgs& A, int lid, unsigned
       const int j0r = 2 * q, j1r = 2 * q + 1;
       const int slot = A.tri ? gtri_prefix(A.ti, jj) + ii : ii * A.tj + jj;
       const cx<T>* pw = reinterpret_cast<const cx<T>*>(A.w) + (long long)slot * N + (long long)i1 * PLANE;
-      for_inputs<C0>(t, [&](int e, int row, int col) { v[e] = pw[row * N3 + col]; });
+      for_inputs<C0>(t, [&](int e, int row, int col) { v[e] = load_stream<T>(&pw[row * N3 + col]); });
       pass_compute<C0, +1, T>(v, tw2, t);
       exchange<C0, C1, N3, SPLIT, T, PAD>(v, smem, t);
       pass_compute<C1, +1, T>(v, tw2, t);
@@ -510,7 +510,10 @@ __device__ __forceinline__ void pencil_body(const PencilArgs& A, int lid, unsign
 
   // (row, col) of the tile = (i1, column c0 + col)
   constexpr int DIR0 = (MODE == PENCIL_INV) ? +1 : -1;
-  for_inputs<P0>(t, [&](int e, int row, int col) { v[e] = base[(long long)row * plane + col]; });
+  if constexpr (MODE == PENCIL_FKI || MODE == PENCIL_FE)
+    for_inputs<P0>(t, [&](int e, int row, int col) { v[e] = load_stream<T>(&base[(long long)row * plane + col]); });
+  else
+    for_inputs<P0>(t, [&](int e, int row, int col) { v[e] = base[(long long)row * plane + col]; });
   pass_compute<P0, DIR0, T>(v, tw1, t);
   exchange<P0, P1, CB, SPLIT, T>(v, smem, t);
   pass_compute<P1, DIR0, T>(v, tw1, t);
@@ -647,7 +650,7 @@ __global__ __launch_bounds__(256) void mac_pair_kernel(MacArgs A) {
     cx<T> v[kMacTile];
 #pragma unroll
     for (int ii = 0; ii < kMacTile; ++ii)
-      if (ii < iend) v[ii] = w[(long long)(tri ? tri_slot(ii, jj) : ii * tj + jj) * N];
+      if (ii < iend) v[ii] = load_stream<T>(&w[(long long)(tri ? tri_slot(ii, jj) : ii * tj + jj) * N]);
     T sx = aj0.x, sy = aj0.y;
 #pragma unroll
     for (int ii = 0; ii < kMacTile; ++ii) {
@@ -718,7 +721,7 @@ __global__ __launch_bounds__(256) void mac_gamma_kernel(MacArgs A, int nreal) {
     for (int ii = 0; ii < kMacTile; ++ii) {
       if (ii < iend) {
         const int i = A.i0 + ii;
-        const cx<T> v = w[(long long)(base + ii * stride) * N];
+        const cx<T> v = load_stream<T>(&w[(long long)(base + ii * stride) * N]);
         const T fi = T(f[i]);
         const T w0 = i <= j0r ? fi : T(0), w1 = (i <= j1r && two) ? fi : T(0);
         sx += w0 * phi_i[ii] * v.x;
