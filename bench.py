@@ -106,6 +106,7 @@ def cpu_baseline(s, c, n=None, ecut=0.0, nocc=None):
     nocc = min(nocc, c.shape[0])
     # fresh interpreters: independent of whatever this process has initialised
     ctx = mp.get_context("spawn")
+    log(f"CPU oracle baseline: {workers} processes")
     with ctx.Pool(workers, initializer=_cpu_init,
                   initargs=(s.a, n, s.miller, ecut, c[:nocc], c[:workers])) as pool:
         pool.map(abs, range(workers))  # start the workers
@@ -137,6 +138,7 @@ def _band_worker(j):
 def cpu_baseline_bands(s, c, w, v, force):
     workers = max(1, min(16, len(os.sched_getaffinity(0))))
     ctx = mp.get_context("spawn")
+    log(f"CPU oracle baseline: {workers} processes")
     with ctx.Pool(workers, initializer=_band_init,
                   initargs=(s.a, tuple(s.n), s.miller, c[:8 * workers], w[:8 * workers], v, force)) as pool:
         pool.map(abs, range(workers))
@@ -152,10 +154,11 @@ def cpu_baseline_bands(s, c, w, v, force):
 # ---------------------------------------------------------------------------
 # Algorithmic bytes of each kernel class over one step (units of N*b).
 # Mirrors the library's schedules: tiles of up to 16 x 16 pairs; one orbital
-# block at q = 0 runs the pair-symmetric schedule (tiles I <= J): FP64 uses
-# a fused inverse + multiply-accumulate for each mirror half (the transform is
-# recomputed, nothing written back), FP32 the parallel inverse plus one pair
-# multiply-accumulate.
+# block at q = 0 runs the pair-symmetric schedule (tiles I <= J, diagonal
+# tiles holding only the pairs ii <= jj): FP64 planes up to 64 wide use a
+# fused inverse + multiply-accumulate for each mirror half (the transform is
+# recomputed, nothing written back), FP32 and wider FP64 planes the parallel
+# in-place inverse plus one pair multiply-accumulate.
 # ---------------------------------------------------------------------------
 def sym_schedule(fp64, n3):
     """The library's default for one block applied to itself (FOCK_SYM_SCHEDULE overrides)."""
@@ -278,16 +281,24 @@ def pmc_traffic(workload, kernel_class):
     return round(1024.0 * (k["fetch_kib"] * rec["fetch_scale"] + k["write_kib"] * rec["write_scale"]))
 
 
+def log(msg):
+    """Progress line on stderr (stdout carries only the JSON line)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def run_steps(step, steps, warmup):
     import torch
     for _ in range(warmup):
         step()
     torch.cuda.synchronize()
+    log(f"{warmup} warmup step(s) done")
     t0 = time.perf_counter()
     for _ in range(steps):
         step()
     torch.cuda.synchronize()
-    return time.perf_counter() - t0
+    dt = time.perf_counter() - t0
+    log(f"{steps} timed step(s): {1e3 * dt / max(steps, 1):.2f} ms per step")
+    return dt
 
 
 def traced(fock, step, steps):
@@ -597,6 +608,7 @@ def main():
         shutil.copyfile(seed_cache, args.tune_cache)
 
     wl = args.workload
+    log(f"workload {wl}")
     rec = {"metric": METRIC, "unit": UNIT, "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "data": "synthetic"}
     if wl in ("c2_fp64", "c3_fp32", "c3_fp64", "c2r_fp64", "c3r_fp32"):
@@ -630,6 +642,7 @@ def main():
     rec["value"] = round(rec["value"], 1)
     rec["ms_per_step"] = round(rec["ms_per_step"], 3)
     if not args.no_compare and wl == "c2_fp64":
+        log("FP32-batched vs FP64-plain comparison")
         rec["fp32_batched_vs_fp64_plain"] = batch_comparison(args, args.tune_cache)
     order = ["metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step", "higher_is_better", "scaling",
              "vs_baseline", "dtype", "data", "config"]

@@ -29,11 +29,12 @@ def kernel_class(name: str):
     m = re.search(r"plane_kernel<\w+, \d+, \d+, \d+, \w+, (\d), \d>", name)
     if m:
         return {"0": "p1_pair_plane_fwd", "1": "p3_plane_inv_mac", "2": "a7_plane_fwd", "3": "plane_inv",
-                "4": "p3_second", "5": "band_plane_density", "6": "band_plane_vmul"}[m.group(1)]
+                "4": "p3_second", "5": "band_plane_density", "6": "band_plane_vmul", "7": "p1_pair_plane_fwd",
+                "8": "p3_plane_inv_mac", "9": "p3_second"}.get(m.group(1))
     m = re.search(r"pencil_kernel<\w+, \d+, \d+, \d+, \w+, (\d), \d>", name)
     if m:
         return {"0": "p2_pencil_kernel", "1": "p2_pencil_energy", "2": "a7_pencil_fwd", "3": "a1_pencil_inv"}[m.group(1)]
-    if "mac_conj_kernel" in name or "mac_pair_kernel" in name:
+    if "mac_conj_kernel" in name or "mac_pair_kernel" in name or "mac_gamma_kernel" in name:
         return "p3_second"
     if "force_gather_kernel" in name:
         return "band_force_gather"
