@@ -427,8 +427,9 @@ constexpr PlaneTune plane_tune(int tbytes, int n2, int n3, int mode) {
   if (tbytes == 8) {  // FP64
     if (band && n2 == 96 && n3 == 128) return PlaneTune{768, true, 1};
     if (n2 == 64 && n3 == 64) {
-      if (pair) return PlaneTune{512, true, 2};
-      if (mirror) return PlaneTune{512, false, 1};
+      if (p1) return PlaneTune{512, true, 1};
+      if (inv) return PlaneTune{512, true, 2};
+      if (mirror) return PlaneTune{512, false, 2};
       return mac ? PlaneTune{256, false, 2} : PlaneTune{256, true, 1};
     }
     if (n2 == 96 && n3 == 128) return pair ? PlaneTune{512, true, 1} : PlaneTune{1024, true, 1};
@@ -439,7 +440,7 @@ constexpr PlaneTune plane_tune(int tbytes, int n2, int n3, int mode) {
     return PlaneTune{192, false, 1};
   }
   if (n2 == 96 && n3 == 128) {
-    if (p1) return PlaneTune{512, true, 2};
+    if (p1) return PlaneTune{512, true, 1};
     if (inv) return PlaneTune{512, true, 1};
     return mode == PLANE_INV_MAC ? PlaneTune{512, false, 1} : PlaneTune{1024, false, 1};
   }
@@ -448,9 +449,9 @@ constexpr PlaneTune plane_tune(int tbytes, int n2, int n3, int mode) {
     if (p1 || fwdmac || mirror) return PlaneTune{720, false, 1};
     return inv ? PlaneTune{720, true, 2} : PlaneTune{576, false, 1};
   }
-  if (n2 == 64 && n3 == 64) return PlaneTune{512, false, 1};
+  if (n2 == 64 && n3 == 64) return p1 ? PlaneTune{256, true, 1} : PlaneTune{512, false, 1};
   if (n2 == 48 && n3 == 64) return PlaneTune{256, false, 1};
-  if (n2 == 48 && n3 == 48) return p1 ? PlaneTune{192, false, 1} : PlaneTune{384, false, 1};
+  if (n2 == 48 && n3 == 48) return p1 ? PlaneTune{192, false, 2} : PlaneTune{384, false, 1};
   return PlaneTune{192, false, 1};
 }
 
