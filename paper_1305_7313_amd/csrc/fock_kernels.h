@@ -477,16 +477,24 @@ __global__ __launch_bounds__(W, MINB) void plane_kernel(PlaneArgs A) {
 // ---------------------------------------------------------------------------
 // Pencil kernel: 1-D FFT along i1 for CB consecutive plane positions.
 // ---------------------------------------------------------------------------
+// cb pencils per workgroup (the host sizes grids and energy partials with
+// it, so it depends on the length and precision only), w threads; split: 1/0
+// forces the two-round FP64 exchange on or off, -1 takes it when the tile
+// exceeds 64 KB; minb: workgroups per CU the registers are budgeted for.
 struct PencilTune {
-  int cb, w;
+  int cb, w, split, minb;
 };
-constexpr PencilTune pencil_tune(int tbytes, int n1) {
-  if (n1 == 24) return PencilTune{64, 128};
-  if (n1 == 48) return PencilTune{64, 128};
-  if (n1 == 64) return PencilTune{64, 256};
-  if (n1 == 72) return tbytes == 4 ? PencilTune{32, 128} : PencilTune{32, 256};
-  if (n1 == 96) return tbytes == 4 ? PencilTune{64, 512} : PencilTune{32, 256};
-  return PencilTune{32, 256};
+constexpr PencilTune pencil_tune(int tbytes, int n1, int mode = -1) {
+  if (n1 == 24) return PencilTune{64, 128, -1, 1};
+  if (n1 == 48) return PencilTune{64, 128, -1, 1};
+  if (n1 == 64) {
+    // FP64 P2: 512 threads on an unsplit 66.5 KB tile, two per CU (-3.5%)
+    if (tbytes == 8 && mode == PENCIL_FKI) return PencilTune{64, 512, 0, 2};
+    return PencilTune{64, 256, -1, 1};
+  }
+  if (n1 == 72) return tbytes == 4 ? PencilTune{32, 128, -1, 1} : PencilTune{32, 256, -1, 1};
+  if (n1 == 96) return tbytes == 4 ? PencilTune{64, 512, -1, 1} : PencilTune{32, 256, -1, 1};
+  return PencilTune{32, 256, -1, 1};
 }
 
 template <typename T, int N1, int CB, int W, bool SPLIT> struct PencilGeom {
@@ -582,9 +590,12 @@ __device__ __forceinline__ void pencil_body(const PencilArgs& A, int lid, unsign
 }
 
 template <typename T, int N1, int MODE> struct PencilCfg {
-  static constexpr int CB = pencil_tune(sizeof(T), N1).cb;
-  static constexpr int W = pencil_tune(sizeof(T), N1).w;
-  static constexpr bool SPLIT = sizeof(T) == 8 && Tile<CB>::slots(N1) * 16 > 65536;
+  static constexpr PencilTune P = pencil_tune(sizeof(T), N1, MODE);
+  static constexpr int CB = P.cb;
+  static constexpr int W = P.w;
+  static constexpr bool SPLIT = P.split >= 0 ? P.split == 1 : sizeof(T) == 8 && Tile<CB>::slots(N1) * 16 > 65536;
+  static constexpr int MINB = P.minb;
+  static_assert(CB == pencil_tune(sizeof(T), N1).cb, "pencils per workgroup must not depend on the mode");
 };
 
 template <typename T, int N1, int CB, int W, bool SPLIT, int MODE, int MINB>

@@ -31,7 +31,7 @@ template <int MODE, int N1>
 hipError_t pencil_go(const PencilArgs& a, int nblocks, hipStream_t s) {
   using T = FX_T;
   using C = PencilCfg<T, N1, MODE>;
-  hipLaunchKernelGGL((pencil_kernel<T, N1, C::CB, C::W, C::SPLIT, MODE, 1>), dim3(nblocks), dim3(C::W), 0, s, a);
+  hipLaunchKernelGGL((pencil_kernel<T, N1, C::CB, C::W, C::SPLIT, MODE, C::MINB>), dim3(nblocks), dim3(C::W), 0, s, a);
   return hipGetLastError();
 }
 template <int N1>
