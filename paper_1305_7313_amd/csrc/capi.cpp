@@ -639,7 +639,7 @@ struct Engine {
           if ((st = tile_forward(la, kp, J.energy, epart)) != FOCK_OK) return st;
           if (J.energy) {
             FX_TRACE(KC_REDUCE);
-            FX_HIP(launch_energy_tile(epart, ngroups, J.fA, J.gB, i0, j0, ti, tj, 0, J.escale, tile_e + tile, s));
+            FX_HIP(launch_energy_tile(epart, ngroups, J.fA, J.gB, i0, j0, ti, tj, 0, 0, J.escale, tile_e + tile, s));
           } else {
             FX_TRACE(KC_P3);
             FX_HIP(launch_plane<T>(PLANE_INV_MAC, P.n[1], P.n[2], la, tj * P.n[0], s));
@@ -662,14 +662,15 @@ struct Engine {
       for (int i0 = 0; i0 <= j0; i0 += T0, ++tile) {
         const int ti = (J.nA - i0) < T0 ? (J.nA - i0) : T0;
         PlaneArgs la = plane_args(phiA, phiA, w, nullptr, J.fA, i0, j0, ti, tj);
-        // diagonal tiles of an apply transform only the pairs ii <= jj
-        // (schedules 1 and 2); the mirror supplies the rest
-        la.tri = !J.energy && i0 == j0 && ti == tj && sym_schedule() != 0;
+        // diagonal tiles transform only the pairs ii <= jj: in an apply
+        // (schedules 1 and 2) the mirror supplies the rest, in an energy the
+        // reduction counts the off-diagonal pairs twice
+        la.tri = i0 == j0 && ti == tj && (J.energy || sym_schedule() != 0);
         const int tt = la.tri ? tri_slot(0, ti) : ti * tj;
         if ((st = tile_forward(la, kp, J.energy, epart)) != FOCK_OK) return st;
         if (J.energy) {
           FX_TRACE(KC_REDUCE);
-          FX_HIP(launch_energy_tile(epart, ngroups, J.fA, J.gB, i0, j0, ti, tj, 1, J.escale, tile_e + tile, s));
+          FX_HIP(launch_energy_tile(epart, ngroups, J.fA, J.gB, i0, j0, ti, tj, 1, la.tri, J.escale, tile_e + tile, s));
           continue;
         }
         if (sym_schedule() == 2) {

@@ -37,7 +37,7 @@ template <typename T> hipError_t launch_force_gather(const ForceArgs& a, int nj,
 hipError_t launch_group_sum(const double* part, int ngrp, long long N, double* rho, hipStream_t s);
 
 hipError_t launch_energy_tile(const double* epart, int ngroups, const double* f, const double* g, int i0, int j0, int ti,
-                              int tj, int sym, double escale, double* tile_e, hipStream_t s);
+                              int tj, int sym, int tri, double escale, double* tile_e, hipStream_t s);
 hipError_t launch_energy_final(const double* tile_e, int ntiles, double scale, double* ex, hipStream_t s);
 hipError_t launch_gb(const KernelParams& kp, const int n[3], const int nq[3], double alpha, double head,
                      double* partial, int nparts, double* k0, hipStream_t s);

@@ -9,11 +9,21 @@ namespace fockx {
 // diagonal tile (i0 == j0) only ii < jj counts twice, ii == jj once.
 __global__ void energy_tile_kernel(const double* __restrict__ epart, int ngroups, const double* __restrict__ f,
                                    const double* __restrict__ g, int i0, int j0, int ti, int tj, int sym,
-                                   double escale, double* __restrict__ tile_e) {
+                                   int tri, double escale, double* __restrict__ tile_e) {
   __shared__ double red[16];
   double acc = 0.0;
-  for (int pr = threadIdx.x; pr < ti * tj; pr += blockDim.x) {
-    const int ii = pr / tj, jj = pr - (pr / tj) * tj;
+  // tri: a diagonal tile holding only the pairs ii <= jj, at tri_slot(ii, jj)
+  const int np = tri ? tri_slot(0, ti) : ti * tj;
+  for (int pr = threadIdx.x; pr < np; pr += blockDim.x) {
+    int ii, jj;
+    if (tri) {
+      jj = 0;
+      while (tri_slot(0, jj + 1) <= pr) ++jj;
+      ii = pr - tri_slot(0, jj);
+    } else {
+      ii = pr / tj;
+      jj = pr - ii * tj;
+    }
     const int i = i0 + ii, j = j0 + jj;
     double wgt = f[i] * g[j];
     if (sym) {
@@ -23,7 +33,6 @@ __global__ void energy_tile_kernel(const double* __restrict__ epart, int ngroups
     if (wgt == 0.0) continue;
     // group-major partials (consecutive threads read consecutive words), four
     // independent partial sums so that the loads overlap; fixed combination order
-    const int np = ti * tj;
     const double* e = epart + pr;
     double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
     int k = 0;
@@ -102,8 +111,8 @@ int pencil_columns(int n1, int tbytes) {
 }
 
 hipError_t launch_energy_tile(const double* epart, int ngroups, const double* f, const double* g, int i0, int j0,
-                              int ti, int tj, int sym, double escale, double* tile_e, hipStream_t s) {
-  hipLaunchKernelGGL(energy_tile_kernel, dim3(1), dim3(256), 0, s, epart, ngroups, f, g, i0, j0, ti, tj, sym,
+                              int ti, int tj, int sym, int tri, double escale, double* tile_e, hipStream_t s) {
+  hipLaunchKernelGGL(energy_tile_kernel, dim3(1), dim3(256), 0, s, epart, ngroups, f, g, i0, j0, ti, tj, sym, tri,
                      escale, tile_e);
   return hipGetLastError();
 }
