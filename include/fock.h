@@ -117,8 +117,10 @@ fock_status fock_energy(const fock_cell *cell, const double q[3], int32_t dtype,
  * grad_tgt[j] = grad_ex * dE/d conj(d_j)  =  grad_ex * 1/2 g_j (V_x psi_j)
  * grad_occ[i] = grad_ex * dE/d conj(c_i)  =  grad_ex * 1/2 f_i (V'_x phi_i)
  * (Wirtinger derivatives; V'_x swaps the two blocks and q -> -q).  Either
- * output may be NULL.  Layouts as the inputs ([nb][ld]).  Pair densities are
- * recomputed, not stored. */
+ * output may be NULL.  Layouts as the inputs ([nb][ld]); only the first npw
+ * columns of each row are written.  Pair densities are recomputed, not
+ * stored.  With occ and tgt the same block (same c, nb, ld and w) at q = 0
+ * the two gradients are equal: one apply fills grad_tgt and is copied. */
 fock_status fock_energy_backward(const fock_cell *cell, const double q[3], int32_t dtype, const fock_orbs *occ,
                                  const fock_orbs *tgt, const double *grad_ex, void *grad_occ, void *grad_tgt,
                                  void *ws, size_t ws_bytes, void *stream);

@@ -1932,6 +1932,18 @@ fock_status fock_energy_backward(const fock_cell* cell, const double q[3], int32
                             : apply_impl<float>(cell, P, q, pr.q_zero, occ, tgt, w, pr.L, s, grad_tgt, s0, tgt->w, grad_ex);
     if (st != FOCK_OK) return st;
   }
+  // One block with equal weights at q = 0: the roles are symmetric and both
+  // gradients are the same array (f_i V_x phi_i / 2); copy instead of a second apply.
+  const bool same = occ->c == tgt->c && occ->nb == tgt->nb && occ->ld == tgt->ld && occ->w == tgt->w;
+  if (grad_occ && grad_tgt && same && pr.q_zero) {
+    if (grad_occ != grad_tgt && occ->nb > 0) {
+      // rows of npw values at the leading dimension ld: padding columns are left alone
+      const size_t eb = dtype == FOCK_C128 ? 16 : 8, pitch = (size_t)occ->ld * eb;
+      FX_HIP(hipMemcpy2DAsync(grad_occ, pitch, grad_tgt, pitch, (size_t)P.npw * eb, (size_t)occ->nb,
+                              hipMemcpyDeviceToDevice, s));
+    }
+    return FOCK_OK;
+  }
   if (grad_occ) {
     // dE/d conj(c_i) = 1/2 f_i (V'_x phi_i): targets act as occupied (weights g), q -> -q
     const double mq[3] = {-q[0], -q[1], -q[2]};
