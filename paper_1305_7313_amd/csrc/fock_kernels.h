@@ -91,6 +91,35 @@ __host__ __device__ constexpr int gtri_prefix(int ti, int jj) {
   return s;
 }
 
+// Both maps enumerate their pairs exactly once, in slots 0 .. count - 1.
+constexpr bool compact_slots_ok() {
+  for (int t = 1; t <= 16; ++t) {
+    bool seen[136] = {};
+    for (int jj = 0; jj < t; ++jj)
+      for (int ii = 0; ii <= jj; ++ii) {
+        const int s = tri_slot(ii, jj);
+        if (s < 0 || s >= tri_slot(0, t) || seen[s]) return false;
+        seen[s] = true;
+      }
+  }
+  for (int ti = 1; ti <= 16; ++ti)
+    for (int tj = 1; tj <= 8; ++tj) {
+      bool seen[128] = {};
+      int n = 0;
+      for (int jj = 0; jj < tj; ++jj)
+        for (int ii = 0; ii < ti; ++ii) {
+          if (ii > 2 * jj + 1) continue;  // i > 2q + 1: all weights zero
+          const int s = gtri_prefix(ti, jj) + ii;
+          if (ii >= gtri_count(ti, jj) || s >= gtri_prefix(ti, tj) || seen[s]) return false;
+          seen[s] = true;
+          ++n;
+        }
+      if (n != gtri_prefix(ti, tj)) return false;
+    }
+  return tri_slot(0, 16) == 136 && gtri_prefix(16, 8) == 72;
+}
+static_assert(compact_slots_ok(), "compact diagonal-tile slot maps");
+
 struct PencilArgs {
   void* x;             // [npairs or nb][N]
   double* epart;       // energy partials [ngroups][npairs] (group-major) or null
