@@ -93,9 +93,14 @@ struct Plan {
   int npw = 0;
   int* d_slot = nullptr;        // [npw] flat box index of each sphere G
   void* d_tw[3] = {nullptr, nullptr, nullptr};  // per axis, length n_a, dtype precision
+  // [n3] per plane column i3: pair densities (support S - S) have no component
+  // (after the transform over the plane axes) at rows |m2| > d_live[i3]; -1:
+  // none in that column.  Null when S - S wraps on this grid.
+  signed char* d_live = nullptr;
   ~Plan() {
     (void)hipSetDevice(device);
     if (d_slot) (void)hipFree(d_slot);
+    if (d_live) (void)hipFree(d_live);
     for (auto p : d_tw)
       if (p) (void)hipFree(p);
   }
@@ -192,6 +197,37 @@ fock_status make_fft_plan(const int n[3], int dtype, std::shared_ptr<Plan>* out)
 }
 
 // Validates the cell and returns (creating if needed) its plan.
+// Columns of the plane axes (i2, i3) that a pair density can occupy.  The
+// sphere S projects onto the plane as a set whose rows, for each m3, span
+// [lo(m3), hi(m3)]; a pair density conj(phi) psi lives on S - S, whose column
+// m3a - m3b reaches |m2| <= max(hi(m3a) - lo(m3b), hi(m3b) - lo(m3a)).  Out:
+// per grid column i3 that bound (-1: empty column).  False when S - S wraps
+// on the grid (2 |m| > n - 1 on a plane axis), where every column is kept.
+bool pair_columns(const fock_cell* cell, std::vector<signed char>* out) {
+  const int n2 = cell->n[1], n3 = cell->n[2];
+  std::map<int, std::pair<int, int>> rows;  // m3 -> [lo, hi] of m2 in the projection of S
+  for (int p = 0; p < cell->npw; ++p) {
+    const int m2 = cell->miller[3 * p + 1], m3 = cell->miller[3 * p + 2];
+    auto it = rows.find(m3);
+    if (it == rows.end()) rows[m3] = {m2, m2};
+    else it->second = {std::min(it->second.first, m2), std::max(it->second.second, m2)};
+  }
+  std::map<int, int> h;  // d3 -> largest |d2|
+  for (const auto& a : rows)
+    for (const auto& b : rows) {
+      const int d3 = a.first - b.first;
+      const int d2 = std::max(a.second.second - b.second.first, b.second.second - a.second.first);
+      auto it = h.find(d3);
+      if (it == h.end() || it->second < d2) h[d3] = d2;
+    }
+  out->assign((size_t)n3, (signed char)-1);
+  for (const auto& e : h) {
+    if (2 * std::abs(e.first) > n3 - 1 || 2 * e.second > n2 - 1 || e.second > 127) return false;
+    (*out)[(size_t)((e.first % n3 + n3) % n3)] = (signed char)e.second;
+  }
+  return true;
+}
+
 fock_status get_plan(const fock_cell* cell, int dtype, std::shared_ptr<Plan>* out) {
   if (!cell) return fail(FOCK_E_ARG, "cell is NULL");
   if (dtype != FOCK_C128 && dtype != FOCK_C64) return fail(FOCK_E_ARG, "dtype must be FOCK_C128 or FOCK_C64");
@@ -261,6 +297,11 @@ fock_status get_plan(const fock_cell* cell, int dtype, std::shared_ptr<Plan>* ou
   p->npw = cell->npw;
   hipError_t e = hipMalloc(&p->d_slot, sizeof(int) * (size_t)cell->npw);
   if (e == hipSuccess) e = hipMemcpy(p->d_slot, slot.data(), sizeof(int) * (size_t)cell->npw, hipMemcpyHostToDevice);
+  std::vector<signed char> live;
+  if (e == hipSuccess && pair_columns(cell, &live)) {
+    e = hipMalloc(&p->d_live, live.size());
+    if (e == hipSuccess) e = hipMemcpy(p->d_live, live.data(), live.size(), hipMemcpyHostToDevice);
+  }
   for (int k = 0; k < 3 && e == hipSuccess; ++k) e = upload_twiddles(cell->n[k], dtype, &p->d_tw[k]);
   if (e != hipSuccess) return fail(FOCK_E_HIP, std::string("plan upload: ") + hipGetErrorString(e));
   std::lock_guard<std::mutex> lk(g_mutex);
@@ -471,6 +512,7 @@ struct Engine {
       FX_HIP(launch_plane<T>(p1_mode, P.n[1], P.n[2], la, tt * P.n[0], s));
     }
     PencilArgs pa{};
+    pa.live = la.live;
     pa.x = la.w;
     pa.epart = energy ? epart : nullptr;
     pa.tw1 = P.d_tw[0];
@@ -519,6 +561,12 @@ struct Engine {
     const int env = e ? std::atoi(e) : -1;
     if (env >= 0 && env <= 2) return env;
     return sizeof(T) == 8 && P.n[2] <= 64 ? 2 : 1;
+  }
+
+  // Live plane columns of the pair buffer (FOCK_PRUNE=0: every column).
+  const signed char* live() const {
+    const char* e = std::getenv("FOCK_PRUNE");
+    return e && e[0] == '0' ? nullptr : P.d_live;
   }
 
   // Gamma tiles: 0 = fused inverse plane FFT + MAC passes (forward, then a
@@ -582,6 +630,7 @@ struct Engine {
         for (int i0 = 0; i0 < J.nA; i0 += T0) {
           const int ti = (J.nA - i0) < T0 ? (J.nA - i0) : T0;
           PlaneArgs la = plane_args(J.phiA, J.phiB, w, nullptr, J.fA, i0, j0, ti, tj);
+          la.live = live();
           if ((st = tile_forward(la, kp, false, nullptr)) != FOCK_OK) return st;
           if (sym_schedule() == 2) {
             PlaneArgs lp = la;
@@ -601,6 +650,7 @@ struct Engine {
             FX_TRACE(KC_P3);
             PlaneArgs lv = plane_args(nullptr, nullptr, nullptr, nullptr, nullptr, 0, 0, 0, 0);
             lv.x = w;
+            lv.live = live();
             lv.nb = ti * tj;
             FX_HIP(launch_plane<T>(PLANE_INV, P.n[1], P.n[2], lv, ti * tj * P.n[0], s));
           }
@@ -636,6 +686,7 @@ struct Engine {
         for (int i0 = 0; i0 < J.nA; i0 += t.ti, ++tile) {
           const int ti = (J.nA - i0) < t.ti ? (J.nA - i0) : t.ti;
           PlaneArgs la = plane_args(J.phiA, J.phiB, w, acc, J.fA, i0, j0, ti, tj);
+          la.live = live();
           if ((st = tile_forward(la, kp, J.energy, epart)) != FOCK_OK) return st;
           if (J.energy) {
             FX_TRACE(KC_REDUCE);
@@ -662,6 +713,7 @@ struct Engine {
       for (int i0 = 0; i0 <= j0; i0 += T0, ++tile) {
         const int ti = (J.nA - i0) < T0 ? (J.nA - i0) : T0;
         PlaneArgs la = plane_args(phiA, phiA, w, nullptr, J.fA, i0, j0, ti, tj);
+        la.live = live();
         // diagonal tiles transform only the pairs ii <= jj: in an apply
         // (schedules 1 and 2) the mirror supplies the rest, in an energy the
         // reduction counts the off-diagonal pairs twice
@@ -714,6 +766,7 @@ struct Engine {
           FX_TRACE(KC_P3);
           PlaneArgs lv = plane_args(nullptr, nullptr, nullptr, nullptr, nullptr, 0, 0, 0, 0);
           lv.x = w;
+          lv.live = live();
           lv.nb = tt;
           FX_HIP(launch_plane<T>(PLANE_INV, P.n[1], P.n[2], lv, tt * P.n[0], s));
         }
@@ -824,6 +877,7 @@ fock_status apply_gamma_impl(const fock_cell* cell, const Plan& P, const fock_or
     for (int i0 = 0; i0 < n && i0 <= 2 * (j0 + tj) - 1; i0 += kGammaTi) {
       const int ti = std::min(kGammaTi, n - i0);
       PlaneArgs la = E.plane_args(pk, pk, ws + L.w, nullptr, o->w, i0, j0, ti, tj);
+      la.live = E.live();
       la.nreal = n;
       // diagonal tile (the occupied reals of the packed targets): only the
       // pairs with a non-zero weight, i <= 2q + 1, are transformed
@@ -835,6 +889,7 @@ fock_status apply_gamma_impl(const fock_cell* cell, const Plan& P, const fock_or
           FX_TRACE(KC_P3);
           PlaneArgs lv = E.plane_args(nullptr, nullptr, nullptr, nullptr, nullptr, 0, 0, 0, 0);
           lv.x = ws + L.w;
+          lv.live = E.live();
           lv.nb = tt;
           FX_HIP(launch_plane<T>(PLANE_INV, P.n[1], P.n[2], lv, tt * P.n[0], s));
         }

@@ -76,7 +76,13 @@ struct PlaneArgs {
   int nreal;           // Gamma modes: number of real orbitals (packed arrays hold ceil(nreal / 2))
   int tri;             // diagonal tile of a self-application (i0 == j0, ti == tj): only the
                        // pairs ii <= jj, pair buffer slot tri_slot(ii, jj)
+  const signed char* live;  // pair-buffer planes: per column i3 the last live row
+                            // (live_row); null: every entry is live
 };
+
+// Row i2 of plane column with bound h (|m2| <= h, h < 0: empty column) holds
+// pair-density data; entries outside are zero and are neither stored nor read.
+template <int N2> __device__ __forceinline__ bool live_row(int i2, int h) { return i2 <= h || i2 >= N2 - h; }
 
 // Slot of pair (ii, jj), ii <= jj, in the pair buffer of a diagonal tile.
 __host__ __device__ constexpr int tri_slot(int ii, int jj) { return jj * (jj + 1) / 2 + ii; }
@@ -121,6 +127,7 @@ constexpr bool compact_slots_ok() {
 static_assert(compact_slots_ok(), "compact diagonal-tile slot maps");
 
 struct PencilArgs {
+  const signed char* live;  // pair buffers: last live row per plane column (see PlaneArgs), or null
   void* x;             // [npairs or nb][N]
   double* epart;       // energy partials [ngroups][npairs] (group-major) or null
   const void* tw1;     // twiddle table, length n1
@@ -237,7 +244,10 @@ __device__ __forceinline__ void plane_body(const PlaneArgs& A, int lid, unsigned
     exchange<C0, C1, N3, SPLIT, T, PAD>(v, smem, t);
     pass_compute<C1, -1, T>(v, tw2, t);
     cx<T>* pw = reinterpret_cast<cx<T>*>(A.w) + (long long)rem * N + (long long)i1 * PLANE;
-    for_outputs<C1>(t, [&](int e, int row, int col) { store_stream<T>(&pw[row * N3 + col], v[e]); });
+    const int hc = A.live ? A.live[t % N3] : N2;  // a column pass: column t % N3 for every value
+    for_outputs<C1>(t, [&](int e, int row, int col) {
+      if (live_row<N2>(row, hc)) store_stream<T>(&pw[row * N3 + col], v[e]);
+    });
   } else if constexpr (MODE == PLANE_INV_MAC || MODE == PLANE_INV_MAC_MIR) {
     // PLANE_INV_MAC: block (jj, i1), loop over ii, acc_j += f_i phi_i v_ij.
     // PLANE_INV_MAC_MIR (one orbital block at q = 0): block (ii, i1), loop over
@@ -250,6 +260,8 @@ __device__ __forceinline__ void plane_body(const PlaneArgs& A, int lid, unsigned
     const int o0 = mir ? A.j0 : A.i0;
     const cx<T>* src = reinterpret_cast<const cx<T>*>(mir ? A.bsrc : A.a);
     const int k0 = A.tri && mir ? bi + 1 : 0, k1 = A.tri && !mir ? bi + 1 : nloop;
+    // every entry is read here: skipping the dead columns (zeros) measured
+    // slower in these register-heavy passes than reading them
     cx<T> s[R1::NV];
 #pragma unroll
     for (int e = 0; e < R1::NV; ++e) s[e] = mk<T>(T(0), T(0));
@@ -305,6 +317,7 @@ __device__ __forceinline__ void plane_body(const PlaneArgs& A, int lid, unsigned
       if (mir) k0 = bi / 2;  // first jj with bi < 2 jj + 2
       else k1 = gtri_count(A.ti, bi);
     }
+    const int hc = A.live ? A.live[t % N3] : N2;  // entries outside are zero: not read
     cx<T> s[R1::NV];
 #pragma unroll
     for (int e = 0; e < R1::NV; ++e) s[e] = mk<T>(T(0), T(0));
@@ -314,7 +327,9 @@ __device__ __forceinline__ void plane_body(const PlaneArgs& A, int lid, unsigned
       const int j0r = 2 * q, j1r = 2 * q + 1;
       const int slot = A.tri ? gtri_prefix(A.ti, jj) + ii : ii * A.tj + jj;
       const cx<T>* pw = reinterpret_cast<const cx<T>*>(A.w) + (long long)slot * N + (long long)i1 * PLANE;
-      for_inputs<C0>(t, [&](int e, int row, int col) { v[e] = load_stream<T>(&pw[row * N3 + col]); });
+      for_inputs<C0>(t, [&](int e, int row, int col) {
+        v[e] = live_row<N2>(row, hc) ? load_stream<T>(&pw[row * N3 + col]) : mk<T>(T(0), T(0));
+      });
       pass_compute<C0, +1, T>(v, tw2, t);
       exchange<C0, C1, N3, SPLIT, T, PAD>(v, smem, t);
       pass_compute<C1, +1, T>(v, tw2, t);
@@ -425,7 +440,10 @@ __device__ __forceinline__ void plane_body(const PlaneArgs& A, int lid, unsigned
   } else {  // PLANE_INV
     const int ob = lid / A.n1, i1 = lid - (lid / A.n1) * A.n1;
     cx<T>* px = reinterpret_cast<cx<T>*>(A.x) + (long long)ob * N + (long long)i1 * PLANE;
-    for_inputs<C0>(t, [&](int e, int row, int col) { v[e] = px[row * N3 + col]; });
+    const int hc = A.live ? A.live[t % N3] : N2;  // pair buffers: entries outside are zero
+    for_inputs<C0>(t, [&](int e, int row, int col) {
+      v[e] = live_row<N2>(row, hc) ? px[row * N3 + col] : mk<T>(T(0), T(0));
+    });
     pass_compute<C0, +1, T>(v, tw2, t);
     exchange<C0, C1, N3, SPLIT, T, PAD>(v, smem, t);
     pass_compute<C1, +1, T>(v, tw2, t);
@@ -546,10 +564,21 @@ __device__ __forceinline__ void pencil_body(const PencilArgs& A, int lid, unsign
   cx<T>* base = reinterpret_cast<cx<T>*>(A.x) + (long long)pr * A.N + c0;
   cx<T> v[Cfg::NV];
 
-  // (row, col) of the tile = (i1, column c0 + col)
+  // (row, col) of the tile = (i1, column c0 + col).  A column pass: every
+  // value of this thread is in column c0 + t % CB.  In pair buffers (live
+  // set) P1 has not stored the dead columns: those pencils are not read and
+  // transform as zero, and the zeros are written (the fused P3 passes read
+  // every column).
   constexpr int DIR0 = (MODE == PENCIL_INV) ? +1 : -1;
+  bool live = true;
+  if (A.live) {
+    const int p = c0 + t % CB, i2 = p / A.n3, i3 = p - i2 * A.n3, h = A.live[i3];
+    live = i2 <= h || i2 >= A.n2 - h;
+  }
   if constexpr (MODE == PENCIL_FKI || MODE == PENCIL_FE)
-    for_inputs<P0>(t, [&](int e, int row, int col) { v[e] = load_stream<T>(&base[(long long)row * plane + col]); });
+    for_inputs<P0>(t, [&](int e, int row, int col) {
+      v[e] = live ? load_stream<T>(&base[(long long)row * plane + col]) : mk<T>(T(0), T(0));
+    });
   else
     for_inputs<P0>(t, [&](int e, int row, int col) { v[e] = base[(long long)row * plane + col]; });
   pass_compute<P0, DIR0, T>(v, tw1, t);
