@@ -168,7 +168,31 @@ def sym_schedule(fp64, n3):
     return 2 if fp64 and n3 <= 64 else 1
 
 
-def step_bytes(nb, N, bpc, fp64, sym=True, sched=None):
+def live_fraction(miller, n):
+    """Fraction of the (i2, i3) plane columns a pair density can occupy (its
+    support S - S projected on the plane axes): the pair-buffer entries P1
+    stores and P2 and the predicated P3 passes read.  1.0 when S - S wraps on
+    the grid (reduced-cutoff grids), where every column is kept."""
+    n2, n3 = n[1], n[2]
+    rows = {}
+    for m2, m3 in zip(miller[:, 1].tolist(), miller[:, 2].tolist()):
+        lo, hi = rows.get(m3, (m2, m2))
+        rows[m3] = (min(lo, m2), max(hi, m2))
+    h = {}
+    for a, (loa, hia) in rows.items():
+        for b, (lob, hib) in rows.items():
+            d3 = a - b
+            h[d3] = max(h.get(d3, -1), hia - lob, hib - loa)
+    col = [-1] * n3
+    for d3, v in h.items():
+        if 2 * abs(d3) > n3 - 1 or 2 * v > n2 - 1:
+            return 1.0
+        col[d3 % n3] = v
+    live = sum(1 for i3 in range(n3) for i2 in range(n2) if i2 <= col[i3] or i2 >= n2 - col[i3])
+    return live / (n2 * n3)
+
+
+def step_bytes(nb, N, bpc, fp64, sym=True, sched=None, lf=1.0):
     T = min(MAC_TILE, nb)
     if sched is None:
         sched = 2 if fp64 else 1
@@ -187,8 +211,10 @@ def step_bytes(nb, N, bpc, fp64, sym=True, sched=None):
             # diagonal tiles of schedules 1 and 2 hold only the pairs ii <= jj
             tri = diag and sched != 0
             npr = ti * (ti + 1) // 2 if tri else ti * tj
-            add("p1_pair_plane_fwd", ti + (0 if diag else tj), npr)
-            add("p2_pencil_kernel", npr, npr)
+            # P1 stores and P2 reads only the live columns (fraction lf); P2
+            # writes the whole pairs, zeros included
+            add("p1_pair_plane_fwd", ti + (0 if diag else tj), npr * lf)
+            add("p2_pencil_kernel", npr * lf, npr)
             if not sym:
                 add("p3_plane_inv_mac", ti * tj + ti + tj, tj)
             elif sched in (0, 2):  # fused P3 into acc_J; mirror: recomputed (2) or from v written back (0)
@@ -197,13 +223,13 @@ def step_bytes(nb, N, bpc, fp64, sym=True, sched=None):
                     add("p3_second", ti * tj + tj + ti, ti)
                 elif tri and ti > 1:
                     add("p3_second", ti * (ti - 1) // 2 + tj + ti, ti)
-            else:  # schedule 1: in-place inverse, one MAC for both halves
-                add("p3_plane_inv_mac", npr, npr)
+            else:  # schedule 1: in-place inverse (reads the live columns), one MAC for both halves
+                add("p3_plane_inv_mac", npr * lf, npr)
                 add("p3_second", npr + ti + (0 if diag else tj) + tj + ti, tj + (0 if diag and not tri else ti))
     return acc
 
 
-def gamma_step_bytes(n, N, bpc, ti_max=16, tj_max=8):
+def gamma_step_bytes(n, N, bpc, ti_max=16, tj_max=8, lf=1.0):
     """Algorithmic bytes per step of the Gamma apply (packed tiles of 16 real
     occupied x 8 packed targets, only tiles holding a pair i <= j)."""
     acc = {}
@@ -223,10 +249,10 @@ def gamma_step_bytes(n, N, bpc, ti_max=16, tj_max=8):
             pi = (ti + 1) // 2  # packed planes holding the tile's occupied orbitals
             # diagonal tile: only the pairs i <= 2q + 1 (non-zero weight)
             npr = sum(min(ti, 2 * jj + 2) for jj in range(tj)) if i0 == 2 * j0 else ti * tj
-            add("p1_pair_plane_fwd", pi + tj, npr)
-            add("p2_pencil_kernel", npr, npr)
-            add("p3_plane_inv_mac", npr + pi + tj, tj)
-            add("p3_second", npr + tj + pi, pi)
+            add("p1_pair_plane_fwd", pi + tj, npr * lf)
+            add("p2_pencil_kernel", npr * lf, npr)
+            add("p3_plane_inv_mac", npr * lf + pi + tj, tj)
+            add("p3_second", npr * lf + tj + pi, pi)
     return acc
 
 
@@ -371,7 +397,7 @@ def single_block(name, args, cpu):
     rec["logical_frac"] = round(rec["logical_hbm_gbs"] / HBM_PEAK_GBS, 4)
     if not args.no_trace:
         tr = traced(fock, step, args.steps)
-        acc = step_bytes(nb, N, bpc, fp64, sched=sym_schedule(fp64, n[2]))
+        acc = step_bytes(nb, N, bpc, fp64, sched=sym_schedule(fp64, n[2]), lf=live_fraction(s.miller, n))
         rec["roofline"] = roofline(tr, acc, args.steps, name)
         rec["kernels"] = {k: {"ms_per_step": round(v[0] / args.steps, 4), "launches_per_step": v[1] / args.steps}
                           for k, v in tr.items() if v[1]}
@@ -412,19 +438,20 @@ def gamma_block(name, args, cpu):
            "cpu_baseline": cpu or None}
     if not args.no_trace:
         tr = traced(fock, step, args.steps)
-        rec["roofline"] = roofline(tr, gamma_step_bytes(nb, N, 16), args.steps, name)
+        rec["roofline"] = roofline(tr, gamma_step_bytes(nb, N, 16, lf=live_fraction(s.miller, s.n)), args.steps, name)
         rec["kernels"] = {k: {"ms_per_step": round(v[0] / args.steps, 4), "launches_per_step": v[1] / args.steps}
                           for k, v in tr.items() if v[1]}
     return rec
 
 
-# Algorithmic bytes per launch of each class on full 16 x 16 tiles (units of
-# N*b), for the k-mesh workload in FP32 (schedule 1): P3 is the in-place
-# inverse plane FFT of the tile, the second pass the streaming MAC of both
-# halves (pair buffer, both orbital tiles, both accumulator tiles read and
-# written).
-TILE_BYTES = {"p1_pair_plane_fwd": 16 + 16 + 256, "p2_pencil_energy": 256, "p2_pencil_kernel": 512,
-              "p3_plane_inv_mac": 256 + 256, "p3_second": 256 + 16 + 16 + 32 + 32}
+def tile_bytes(lf):
+    """Algorithmic bytes per launch of each class on full 16 x 16 tiles (units
+    of N*b), for the k-mesh workload in FP32 (schedule 1): P3 is the in-place
+    inverse plane FFT of the tile, the second pass the streaming MAC of both
+    halves (pair buffer, both orbital tiles, both accumulator tiles read and
+    written).  lf: live fraction of the pair-buffer columns."""
+    return {"p1_pair_plane_fwd": 16 + 16 + 256 * lf, "p2_pencil_energy": 256 * lf, "p2_pencil_kernel": 256 * lf + 256,
+            "p3_plane_inv_mac": 256 * lf + 256, "p3_second": 256 + 16 + 16 + 32 + 32}
 
 
 def kmesh_grad(name, args, cpu):
@@ -465,7 +492,8 @@ def kmesh_grad(name, args, cpu):
            "cpu_baseline": cpu or None}
     if not args.no_trace:
         tr = traced(fock, step, 1)
-        acc = {k: [TILE_BYTES[k] * N * 8 * tr[k][1], tr[k][1]] for k in TILE_BYTES if k in tr and tr[k][1]}
+        tb = tile_bytes(live_fraction(s.miller, n))
+        acc = {k: [tb[k] * N * 8 * tr[k][1], tr[k][1]] for k in tb if k in tr and tr[k][1]}
         rec["roofline"] = roofline(tr, acc, 1, name)
         rec["kernels"] = {k: {"ms_per_step": round(v[0], 4), "launches_per_step": v[1]} for k, v in tr.items() if v[1]}
     return rec
