@@ -1,0 +1,63 @@
+"""The benchmark's byte model (the roofline denominators), on the CPU.
+
+* The live plane columns of the pair buffer cover the exact support of
+  S - S (every difference of two sphere vectors, projected on the plane
+  axes), on cubic and skewed cells, and fall back to every column when
+  S - S wraps on the grid.
+* The per-launch pair counts of the symmetric schedule reproduce the tile
+  structure: 36 launches and 8256 transformed pairs for 128 orbitals, the
+  figures the PMC traffic of config 2 was checked against.
+"""
+import numpy as np
+
+import bench
+import synth
+
+
+def _exact_support(miller):
+    p = np.unique(miller[:, 1:3], axis=0)
+    d = (p[:, None, :] - p[None, :, :]).reshape(-1, 2)
+    return np.unique(d, axis=0)
+
+
+def _live_table(miller, n):
+    # the rule as bench.live_fraction states it, kept per column for the check
+    n2, n3 = n[1], n[2]
+    rows = {}
+    for m2, m3 in zip(miller[:, 1].tolist(), miller[:, 2].tolist()):
+        lo, hi = rows.get(m3, (m2, m2))
+        rows[m3] = (min(lo, m2), max(hi, m2))
+    col = [-1] * n3
+    for a, (loa, hia) in rows.items():
+        for b, (lob, hib) in rows.items():
+            col[(a - b) % n3] = max(col[(a - b) % n3], hia - lob, hib - loa)
+    return col
+
+
+def test_live_columns_cover_the_pair_support():
+    skew = np.array([[10.0, 0.0, 0.0], [1.0, 18.0, 0.0], [0.5, 0.3, 24.0]])
+    for a, n in ((synth.cubic_cell(10.0), (24, 24, 24)), (skew, (24, 48, 64)), (synth.cubic_cell(20.0), (64, 64, 64))):
+        s = synth.make_system(a, n)
+        col = _live_table(s.miller, s.n)
+        sup = _exact_support(s.miller)
+        for d2, d3 in sup:
+            i2, h = d2 % n[1], col[d3 % n[2]]
+            assert i2 <= h or i2 >= n[1] - h, (n, d2, d3, h)
+        lf = bench.live_fraction(s.miller, s.n)
+        assert len(sup) <= lf * n[1] * n[2] + 1e-9
+        assert 0.5 < lf < 0.8
+
+
+def test_live_fraction_is_one_when_the_support_wraps():
+    s = synth.make_system(synth.cubic_cell(20.0), (64, 64, 64))
+    assert bench.live_fraction(s.miller, (48, 48, 48)) == 1.0
+
+
+def test_step_bytes_tile_structure():
+    acc = bench.step_bytes(128, 1, 1, True, sched=2)
+    b, launches = acc["p2_pencil_kernel"]
+    assert launches == 36
+    assert b == 2 * (28 * 256 + 8 * 136)  # pairs read and written, N*b units
+    lf = 0.75
+    b2, _ = bench.step_bytes(128, 1, 1, True, sched=2, lf=lf)["p2_pencil_kernel"]
+    assert abs(b2 - (1 + lf) * (28 * 256 + 8 * 136)) < 1e-9
