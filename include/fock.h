@@ -183,8 +183,18 @@ fock_status fock_batch_plan_create(const fock_cell *cells, const fock_orbs *occ,
  * g = tgt[s].w (device FP64 [nsys]; NULL: not copied). */
 fock_status fock_batch_apply(void *plan, void *const *vx_out, double *ex_out, void *stream);
 /* Synchronises the device and reports a scheduler abort (a dependency wait
- * of the persistent kernel that exceeded its poll limit) as FOCK_E_HIP. */
+ * of the persistent kernel that exceeded its time bound) as FOCK_E_HIP.  The
+ * aborted replay's results are undefined; the next replay starts afresh. */
 fock_status fock_batch_check(void *plan);
+/* Failure detection of the persistent schedule: bound, in milliseconds of
+ * the device's constant wall clock, on one dependency wait of a work unit.
+ * A wait past it raises the plan's abort flag; every block then stops taking
+ * work and the launch drains (no hang), and fock_batch_check reports it.
+ * The plan's own bound is 1 s or four times its tuned replay time, whichever
+ * is longer (waits in a correct schedule last milliseconds); ms <= 0 restores
+ * it.  Takes effect from the next replay; synchronous (a host-to-device copy).
+ * Plans without the persistent kernel accept and ignore it. */
+fock_status fock_batch_set_wait_limit(void *plan, double ms);
 /* JSON description of the chosen schedule (owned by the plan). */
 const char *fock_batch_plan_info(void *plan);
 void fock_batch_plan_destroy(void *plan);

@@ -13,8 +13,10 @@
 // each unit's segment are complete, runs the unit, and adds to the segment's
 // done counter.  Tickets are taken only by running blocks, in order, so every
 // wait is on work already held by a running block: the launch cannot deadlock
-// whatever the grid size.  Waits are bounded; a block that exceeds the bound
-// raises the abort flag, and every block stops taking work once it is set.
+// whatever the grid size.  Waits are bounded in time (the device's constant
+// wall clock); a block whose wait exceeds the bound raises the abort flag,
+// and every block stops taking work once it is set, so the launch always
+// drains.
 #pragma once
 
 #include "fock_kernels.h"
@@ -54,7 +56,7 @@ struct BatchArgs {
   unsigned long long* ticket;    // next unit to hand out
   int* done;                     // per segment: finished units
   int* abort_flag;               // set by a block whose wait exceeded the bound
-  long long spin_limit;          // bound on polls of one dependency
+  const long long* wait_ticks;   // device: bound on one dependency wait, wall-clock ticks
 };
 
 // Multiply-accumulate of one chunk of grid points (the pair-symmetric
@@ -238,10 +240,11 @@ __device__ __forceinline__ void batch_kernel_body(const BatchArgs& B) {
           const int dep = B.seg[gi].dep[d];
           if (dep < 0) continue;
           const int need = B.seg[dep].units;
-          long long spins = 0;
+          const long long limit = *B.wait_ticks;
+          const long long t_wait = wall_clock64();
           while (__hip_atomic_load(&B.done[dep], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < need) {
             if (__hip_atomic_load(B.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
-                ++spins > B.spin_limit) {
+                wall_clock64() - t_wait > limit) {
               __hip_atomic_store(B.abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
               go = 0;
               break;

@@ -16,6 +16,7 @@
 
 #include "../../include/fock.h"
 #include "fock_launch.h"
+#include "tune_cache.h"
 
 using namespace fockx;
 
@@ -97,7 +98,9 @@ struct Plan {
   // (after the transform over the plane axes) at rows |m2| > d_live[i3]; -1:
   // none in that column.  Null when S - S wraps on this grid.
   signed char* d_live = nullptr;
+  bool owns = true;  // false: the device tables live in memory the plan does not own
   ~Plan() {
+    if (!owns) return;
     (void)hipSetDevice(device);
     if (d_slot) (void)hipFree(d_slot);
     if (d_live) (void)hipFree(d_live);
@@ -140,22 +143,28 @@ void reciprocal(const double a[3][3], double b[3][3], double* omega) {
   }
 }
 
-// tw[m] = exp(-2 pi i m / n), computed in FP64, rounded once for FP32.
-hipError_t upload_twiddles(int n, int dtype, void** out) {
-  const size_t bytes = (size_t)n * (dtype == FOCK_C128 ? 16 : 8);
-  hipError_t e = hipMalloc(out, bytes);
-  if (e != hipSuccess) return e;
-  std::vector<double> d(2 * n);
-  std::vector<float> f(2 * n);
+// tw[m] = exp(-2 pi i m / n), computed in FP64, rounded once for FP32; as
+// the bytes of the dtype's complex array.
+std::vector<unsigned char> host_twiddles(int n, int dtype) {
+  std::vector<unsigned char> out((size_t)n * (dtype == FOCK_C128 ? 16 : 8));
   for (int m = 0; m < n; ++m) {
     const CosSin cs = cossin_2pi(m, n);
-    d[2 * m] = cs.c;
-    d[2 * m + 1] = -cs.s;
-    f[2 * m] = (float)cs.c;
-    f[2 * m + 1] = (float)(-cs.s);
+    if (dtype == FOCK_C128) {
+      const double v[2] = {cs.c, -cs.s};
+      std::memcpy(out.data() + 16 * (size_t)m, v, sizeof v);
+    } else {
+      const float v[2] = {(float)cs.c, (float)(-cs.s)};
+      std::memcpy(out.data() + 8 * (size_t)m, v, sizeof v);
+    }
   }
-  return hipMemcpy(*out, dtype == FOCK_C128 ? (const void*)d.data() : (const void*)f.data(), bytes,
-                   hipMemcpyHostToDevice);
+  return out;
+}
+
+hipError_t upload_twiddles(int n, int dtype, void** out) {
+  const std::vector<unsigned char> t = host_twiddles(n, dtype);
+  hipError_t e = hipMalloc(out, t.size());
+  if (e != hipSuccess) return e;
+  return hipMemcpy(*out, t.data(), t.size(), hipMemcpyHostToDevice);
 }
 
 int tbytes_of(int dtype) { return dtype == FOCK_C128 ? 8 : 4; }
@@ -228,7 +237,9 @@ bool pair_columns(const fock_cell* cell, std::vector<signed char>* out) {
   return true;
 }
 
-fock_status get_plan(const fock_cell* cell, int dtype, std::shared_ptr<Plan>* out) {
+// Host checks of the cell fields a plan depends on; the reciprocal lattice
+// and the volume.
+fock_status check_plan_cell(const fock_cell* cell, int dtype, double b[3][3], double* omega) {
   if (!cell) return fail(FOCK_E_ARG, "cell is NULL");
   if (dtype != FOCK_C128 && dtype != FOCK_C64) return fail(FOCK_E_ARG, "dtype must be FOCK_C128 or FOCK_C64");
   for (int k = 0; k < 3; ++k)
@@ -239,9 +250,9 @@ fock_status get_plan(const fock_cell* cell, int dtype, std::shared_ptr<Plan>* ou
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j)
       if (!std::isfinite(cell->a[i][j])) return fail(FOCK_E_ARG, "lattice vectors must be finite");
-  double b[3][3], omega = 0.0;
-  reciprocal(cell->a, b, &omega);
-  if (!(omega > 1e-12)) return fail(FOCK_E_ARG, "cell volume is not positive");
+  double om = 0.0;
+  reciprocal(cell->a, b, &om);
+  if (!(om > 1e-12)) return fail(FOCK_E_ARG, "cell volume is not positive");
   if (cell->g0 != FOCK_G0_ZERO && cell->g0 != FOCK_G0_GB) return fail(FOCK_E_ARG, "g0 must be ZERO or GB");
   if (cell->g0 == FOCK_G0_GB) {
     if (!(cell->gb_alpha > 0.0) || !std::isfinite(cell->gb_alpha)) return fail(FOCK_E_ARG, "gb_alpha must be > 0");
@@ -249,7 +260,42 @@ fock_status get_plan(const fock_cell* cell, int dtype, std::shared_ptr<Plan>* ou
       if (cell->nq[k] < 1) return fail(FOCK_E_ARG, "nq must be >= 1");
   }
   if (std::isnan(cell->ecut_fock)) return fail(FOCK_E_ARG, "ecut_fock is NaN");
+  *omega = om;
+  return FOCK_OK;
+}
 
+// Sphere tables: the box slot of every G (each G its own slot, inside the
+// box) and the live plane columns of a pair density (has_live false when
+// S - S wraps on the grid).
+fock_status sphere_tables(const fock_cell* cell, std::vector<int>* slot, std::vector<signed char>* live,
+                          bool* has_live) {
+  const long long N = (long long)cell->n[0] * cell->n[1] * cell->n[2];
+  slot->assign((size_t)cell->npw, 0);
+  std::vector<unsigned char> seen((size_t)N, 0);
+  for (int p = 0; p < cell->npw; ++p) {
+    int idx[3];
+    for (int k = 0; k < 3; ++k) {
+      const int m = cell->miller[3 * p + k];
+      if (2 * (long long)std::abs(m) > (long long)cell->n[k] - 1) {
+        char buf[160];
+        std::snprintf(buf, sizeof buf, "Miller index %d on axis %d does not fit the box n=%d", m, k, cell->n[k]);
+        return fail(FOCK_E_ALIAS, buf);
+      }
+      idx[k] = (m % cell->n[k] + cell->n[k]) % cell->n[k];
+    }
+    const long long flat = ((long long)idx[0] * cell->n[1] + idx[1]) * cell->n[2] + idx[2];
+    if (seen[flat]) return fail(FOCK_E_ALIAS, "repeated G-vector in the sphere list");
+    seen[flat] = 1;
+    (*slot)[p] = (int)flat;
+  }
+  *has_live = pair_columns(cell, live);
+  return FOCK_OK;
+}
+
+fock_status get_plan(const fock_cell* cell, int dtype, std::shared_ptr<Plan>* out) {
+  double b[3][3], omega = 0.0;
+  fock_status st0 = check_plan_cell(cell, dtype, b, &omega);
+  if (st0 != FOCK_OK) return st0;
   int dev = 0;
   const bool have_dev = hipGetDevice(&dev) == hipSuccess;
   const size_t mbytes = (size_t)cell->npw * 3 * sizeof(int32_t);
@@ -267,24 +313,10 @@ fock_status get_plan(const fock_cell* cell, int dtype, std::shared_ptr<Plan>* ou
   // Sphere check (host only): every G has its own box slot.  Whether pair
   // products alias depends on q and the cutoff: check_alias, per call.
   const long long N = (long long)cell->n[0] * cell->n[1] * cell->n[2];
-  std::vector<int> slot(cell->npw);
-  std::vector<unsigned char> seen((size_t)N, 0);
-  for (int p = 0; p < cell->npw; ++p) {
-    int idx[3];
-    for (int k = 0; k < 3; ++k) {
-      const int m = cell->miller[3 * p + k];
-      if (2 * (long long)std::abs(m) > (long long)cell->n[k] - 1) {
-        char buf[160];
-        std::snprintf(buf, sizeof buf, "Miller index %d on axis %d does not fit the box n=%d", m, k, cell->n[k]);
-        return fail(FOCK_E_ALIAS, buf);
-      }
-      idx[k] = (m % cell->n[k] + cell->n[k]) % cell->n[k];
-    }
-    const long long flat = ((long long)idx[0] * cell->n[1] + idx[1]) * cell->n[2] + idx[2];
-    if (seen[flat]) return fail(FOCK_E_ALIAS, "repeated G-vector in the sphere list");
-    seen[flat] = 1;
-    slot[p] = (int)flat;
-  }
+  std::vector<int> slot;
+  std::vector<signed char> live;
+  bool has_live = false;
+  if ((st0 = sphere_tables(cell, &slot, &live, &has_live)) != FOCK_OK) return st0;
   if (!have_dev) return fail(FOCK_E_HIP, "no HIP device available");
   auto p = std::make_shared<Plan>();
   p->device = dev;
@@ -297,8 +329,7 @@ fock_status get_plan(const fock_cell* cell, int dtype, std::shared_ptr<Plan>* ou
   p->npw = cell->npw;
   hipError_t e = hipMalloc(&p->d_slot, sizeof(int) * (size_t)cell->npw);
   if (e == hipSuccess) e = hipMemcpy(p->d_slot, slot.data(), sizeof(int) * (size_t)cell->npw, hipMemcpyHostToDevice);
-  std::vector<signed char> live;
-  if (e == hipSuccess && pair_columns(cell, &live)) {
+  if (e == hipSuccess && has_live) {
     e = hipMalloc(&p->d_live, live.size());
     if (e == hipSuccess) e = hipMemcpy(p->d_live, live.data(), live.size(), hipMemcpyHostToDevice);
   }
@@ -1367,17 +1398,6 @@ fock_status band_force_impl(const Plan& P, const double k[3], const fock_orbs* o
 // ---------------------------------------------------------------------------
 // Batched form: several systems, one persistent launch inside one hipGraph.
 // ---------------------------------------------------------------------------
-struct BatchParams {
-  int tile = 16;            // pair tile edge (<= kMacTile)
-  int slots = 6;            // pair buffers in flight (>= 4)
-  int units_per_ticket = 8;
-  int blocks_per_cu = 1;    // persistent blocks per CU (selects the register budget)
-  double ms = 0.0;          // measured replay time when tuned
-  // 0: one persistent kernel runs every stage of every system; 1: the graph
-  // holds each system's own schedule of per-shape kernels, one after another
-  int mode = 0;
-};
-
 struct BatchPlanImpl {
   int device = 0, dtype = 0, nsys = 0, cus = 0;
   std::vector<std::shared_ptr<Plan>> plans;
@@ -1401,6 +1421,9 @@ struct BatchPlanImpl {
   unsigned long long* d_ticket = nullptr;
   int* d_done = nullptr;
   int* d_abort = nullptr;
+  long long* d_wait = nullptr;  // bound on one dependency wait of the persistent kernel, wall-clock ticks
+  double wait_khz = 0.0;        // wall-clock ticks per millisecond
+  double wait_ms = 0.0;         // the plan's own bound (fock_batch_set_wait_limit with ms <= 0 restores it)
   std::vector<void*> slot_mem;
   size_t slot_bytes = 0;
   int nseg = 0;
@@ -1427,6 +1450,20 @@ struct BatchPlanImpl {
     return FOCK_OK;
   }
 };
+
+// A dependency wait of the persistent kernel lasts, in a correct schedule, at
+// most until the running blocks finish the units they hold (tickets are
+// handed out in dependency order): milliseconds.  The bound is 1 s, or four
+// times the tuned replay if that is longer, so a scheduling fault ends the
+// launch with FOCK_E_HIP from fock_batch_check instead of a long hang.
+constexpr double kBatchWaitMs = 1000.0;
+
+fock_status batch_set_wait(BatchPlanImpl& B, double ms) {
+  if (!B.d_wait) return FOCK_OK;
+  const long long ticks = std::max(1LL, (long long)std::llround(ms * B.wait_khz));
+  FX_HIP(hipMemcpy(B.d_wait, &ticks, sizeof ticks, hipMemcpyHostToDevice));
+  return FOCK_OK;
+}
 
 // Builds the unit list: system-interleaved pair tiles (per system: target tile
 // outer, occupied tile I <= J inner, the order of the single-system symmetric
@@ -1563,7 +1600,7 @@ fock_status batch_capture(BatchPlanImpl& B, const BatchParams& prm) {
     a.ticket = B.d_ticket;
     a.done = B.d_done;
     a.abort_flag = B.d_abort;
-    a.spin_limit = 400000000ll;  // polls of ~0.1 us each: far beyond any real wait
+    a.wait_ticks = B.d_wait;
     occ = prm.blocks_per_cu >= 2 ? 2 : 1;
     const int bpc_max = batch_blocks_per_cu<T>(occ);
     bpc = prm.blocks_per_cu > 0 && prm.blocks_per_cu < bpc_max ? prm.blocks_per_cu : bpc_max;
@@ -1659,61 +1696,6 @@ std::string batch_signature(const BatchPlanImpl& B) {
   return key;
 }
 
-bool tune_cache_lookup(const std::string& path, const std::string& key, BatchParams* out) {
-  if (path.empty()) return false;
-  FILE* f = std::fopen(path.c_str(), "r");
-  if (!f) return false;
-  char line[4096];
-  bool found = false;
-  const std::string pat = "\"" + key + "\": {";
-  while (std::fgets(line, sizeof line, f)) {
-    const char* at = std::strstr(line, pat.c_str());
-    if (!at) continue;
-    BatchParams p;
-    // entries written before the mode field existed describe the persistent kernel
-    if (std::sscanf(at + pat.size(),
-                    " \"tile\": %d, \"slots\": %d, \"units_per_ticket\": %d, \"blocks_per_cu\": %d, \"ms\": %lf, "
-                    "\"mode\": %d",
-                    &p.tile, &p.slots, &p.units_per_ticket, &p.blocks_per_cu, &p.ms, &p.mode) >= 5) {
-      *out = p;
-      found = true;
-    }
-  }
-  std::fclose(f);
-  return found;
-}
-
-void tune_cache_store(const std::string& path, const std::string& key, const BatchParams& p) {
-  if (path.empty()) return;
-  std::vector<std::string> keep;
-  if (FILE* f = std::fopen(path.c_str(), "r")) {
-    char line[4096];
-    const std::string pat = "\"" + key + "\": {";
-    while (std::fgets(line, sizeof line, f)) {
-      std::string l(line);
-      if (l.find("\": {") != std::string::npos && l.find(pat) == std::string::npos) {
-        while (!l.empty() && (l.back() == '\n' || l.back() == ',')) l.pop_back();
-        keep.push_back(l);
-      }
-    }
-    std::fclose(f);
-  }
-  char buf[512];
-  std::snprintf(buf, sizeof buf,
-                "\"%s\": {\"tile\": %d, \"slots\": %d, \"units_per_ticket\": %d, \"blocks_per_cu\": %d, \"ms\": %.4f, "
-                "\"mode\": %d}",
-                key.c_str(), p.tile, p.slots, p.units_per_ticket, p.blocks_per_cu, p.ms, p.mode);
-  keep.push_back(buf);
-  const std::string tmp = path + ".tmp";
-  FILE* f = std::fopen(tmp.c_str(), "w");
-  if (!f) return;
-  std::fprintf(f, "{\n");
-  for (size_t k = 0; k < keep.size(); ++k) std::fprintf(f, "%s%s\n", keep[k].c_str(), k + 1 < keep.size() ? "," : "");
-  std::fprintf(f, "}\n");
-  std::fclose(f);
-  std::rename(tmp.c_str(), path.c_str());
-}
-
 template <typename T>
 fock_status batch_time(BatchPlanImpl& B, double* ms) {
   hipEvent_t a = nullptr, b = nullptr;
@@ -1748,7 +1730,12 @@ fock_status batch_tune_and_capture(BatchPlanImpl& B, const std::string& cache) {
   int force_mode = me && (std::atoi(me) == 0 || std::atoi(me) == 1) ? std::atoi(me) : -1;
   if (!B.persistent_ok) force_mode = 1;  // only the per-shape schedules apply
   if (!tune) {
+    // untuned: the default schedule; FOCK_BATCH_TICKET sets the units per ticket
     best.mode = force_mode == 1 ? 1 : 0;
+    if (const char* tk = std::getenv("FOCK_BATCH_TICKET")) {
+      const int v = std::atoi(tk);
+      if (v >= 1 && v <= (1 << 20)) best.units_per_ticket = v;
+    }
   } else if (force_mode >= 0 || !tune_cache_lookup(cache, key, &best)) {
     std::map<std::tuple<int, int, int>, double> seen;
     auto eval = [&](int tile, int upt, int bpc, double* ms) -> fock_status {
@@ -1821,6 +1808,9 @@ fock_status batch_tune_and_capture(BatchPlanImpl& B, const std::string& cache) {
     if (force_mode < 0) tune_cache_store(cache, key, best);
   }
   B.prm = best;
+  B.wait_ms = std::max(kBatchWaitMs, 4.0 * best.ms);
+  fock_status st = batch_set_wait(B, B.wait_ms);
+  if (st != FOCK_OK) return st;
   return batch_capture<T>(B, best);
 }
 
@@ -1846,6 +1836,13 @@ fock_status batch_create(BatchPlanImpl& B, const std::string& cache) {
   if ((st = B.alloc(&p, sizeof(int))) != FOCK_OK) return st;
   B.d_abort = static_cast<int*>(p);
   FX_HIP(hipMemset(B.d_abort, 0, sizeof(int)));
+  if ((st = B.alloc(&p, sizeof(long long))) != FOCK_OK) return st;
+  B.d_wait = static_cast<long long*>(p);
+  int khz = 0;
+  FX_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, B.device));
+  B.wait_khz = khz > 0 ? (double)khz : 1.0e5;
+  B.wait_ms = kBatchWaitMs;
+  if ((st = batch_set_wait(B, B.wait_ms)) != FOCK_OK) return st;
   FX_HIP(hipStreamCreateWithFlags(&B.cap, hipStreamNonBlocking));
   if (!B.persistent_ok) return batch_tune_and_capture<T>(B, cache);
   // the persistent kernel's state
@@ -1885,15 +1882,14 @@ fock_status batch_create(BatchPlanImpl& B, const std::string& cache) {
   B.d_sys = static_cast<BatchSys*>(p);
   FX_HIP(hipMemcpy(B.d_sys, sys.data(), sizeof(BatchSys) * B.nsys, hipMemcpyHostToDevice));
   // pair buffers: sized for the largest tile of the largest grid
-  const int max_slots = 6;
   B.slot_bytes = cb * (size_t)nmax * kMacTile * kMacTile;
-  for (int k = 0; k < max_slots; ++k) {
+  for (int k = 0; k < kBatchSlots; ++k) {
     if ((st = B.alloc(&p, B.slot_bytes)) != FOCK_OK) return st;
     B.slot_mem.push_back(p);
   }
-  if ((st = B.alloc(&p, sizeof(void*) * max_slots)) != FOCK_OK) return st;
+  if ((st = B.alloc(&p, sizeof(void*) * kBatchSlots)) != FOCK_OK) return st;
   B.d_slots = static_cast<void**>(p);
-  FX_HIP(hipMemcpy(B.d_slots, B.slot_mem.data(), sizeof(void*) * max_slots, hipMemcpyHostToDevice));
+  FX_HIP(hipMemcpy(B.d_slots, B.slot_mem.data(), sizeof(void*) * kBatchSlots, hipMemcpyHostToDevice));
   if ((st = B.alloc(&p, sizeof(unsigned long long))) != FOCK_OK) return st;
   B.d_ticket = static_cast<unsigned long long*>(p);
   return batch_tune_and_capture<T>(B, cache);
@@ -2235,6 +2231,14 @@ fock_status fock_batch_check(void* plan) {
   if (e != hipSuccess) return fail(FOCK_E_HIP, std::string("batch check: ") + hipGetErrorString(e));
   if (aborted) return fail(FOCK_E_HIP, "batch scheduler aborted a dependency wait");
   return FOCK_OK;
+}
+
+fock_status fock_batch_set_wait_limit(void* plan, double ms) {
+  if (!plan) return fail(FOCK_E_ARG, "plan is NULL");
+  if (std::isnan(ms)) return fail(FOCK_E_ARG, "ms is NaN");
+  BatchPlanImpl* B = static_cast<BatchPlanImpl*>(plan);
+  (void)hipSetDevice(B->device);
+  return batch_set_wait(*B, ms > 0.0 ? ms : B->wait_ms);
 }
 
 const char* fock_batch_plan_info(void* plan) {

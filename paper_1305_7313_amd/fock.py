@@ -96,6 +96,8 @@ def lib():
         L.fock_batch_apply.argtypes = [ctypes.c_void_p, P(ctypes.c_void_p), ctypes.c_void_p, ctypes.c_void_p]
         L.fock_batch_check.restype = ctypes.c_int
         L.fock_batch_check.argtypes = [ctypes.c_void_p]
+        L.fock_batch_set_wait_limit.restype = ctypes.c_int
+        L.fock_batch_set_wait_limit.argtypes = [ctypes.c_void_p, ctypes.c_double]
         L.fock_batch_plan_info.restype = ctypes.c_char_p
         L.fock_batch_plan_info.argtypes = [ctypes.c_void_p]
         L.fock_batch_plan_destroy.restype = None
@@ -181,13 +183,40 @@ def dtype_code(t) -> int:
     raise TypeError(f"orbital coefficients must be complex128 or complex64, not {t.dtype}")
 
 
-def orbs(c, w) -> fock_orbs:
-    """fock_orbs over a device tensor c [nb, ld] (row-major) and weights w [nb] (float64)."""
+def _like(t, ref, name):
+    """t must hold ref's dtype on ref's device: the library reads and writes
+    every complex array of a call at the element size of one dtype."""
+    if t.dtype != ref.dtype:
+        raise ValueError(f"{name} is {t.dtype}; every coefficient, output and gradient of this call must be "
+                         f"{ref.dtype}")
+    if t.device != ref.device:
+        raise ValueError(f"{name} is on {t.device}, not on {ref.device}")
+
+
+def _rows(t, ref, name, nb, npw, ld=None):
+    """t: [>= nb, >= npw] rows of ref's dtype and device, unit stride along G,
+    and (with more than one row) the leading dimension ld the library uses."""
+    _like(t, ref, name)
+    if t.dim() != 2 or t.stride(1) != 1:
+        raise ValueError(f"{name} must be [nb, npw] with unit stride along G")
+    if t.shape[0] < nb or t.shape[1] < npw:
+        raise ValueError(f"{name} is {tuple(t.shape)}, smaller than [{nb}, {npw}]")
+    if ld is not None and nb > 1 and t.stride(0) != ld:
+        raise ValueError(f"{name} must have the leading dimension {ld} of its coefficient block")
+
+
+def orbs(c, w, npw=None) -> fock_orbs:
+    """fock_orbs over a device tensor c [nb, ld] (row-major) and weights w [nb]
+    (float64, on c's device); npw: the sphere size every row must hold."""
     import torch
     if c.dim() != 2 or c.stride(1) != 1:
         raise ValueError("coefficients must be [nb, ld] with unit stride along G")
+    if npw is not None and c.shape[0] > 0 and c.shape[1] < npw:
+        raise ValueError(f"coefficients hold {c.shape[1]} plane waves per row, fewer than the sphere's {npw}")
     if w.dtype != torch.float64 or not w.is_contiguous():
         raise ValueError("weights must be a contiguous float64 tensor")
+    if w.device != c.device:
+        raise ValueError(f"weights are on {w.device}, the coefficients on {c.device}")
     if w.numel() != c.shape[0]:
         raise ValueError("one weight per orbital")
     o = fock_orbs()
@@ -212,11 +241,10 @@ def fock_apply_gamma(cell: Cell, c, f, out=None, ws=None):
     (C call: fock_apply_gamma; c must hold c(-G) = conj(c(G)))."""
     import torch
     dt = dtype_code(c)
+    o = orbs(c, f, cell.npw)
     if out is None:
         out = torch.empty((c.shape[0], cell.npw), dtype=c.dtype, device=c.device)
-    o = orbs(c, f)
-    if out.shape[0] > 1 and out.stride(0) != o.ld:
-        raise ValueError("out must have the orbitals' leading dimension")
+    _rows(out, c, "out", o.nb, cell.npw, o.ld)
     if ws is None:
         nbytes = int(lib().fock_workspace_size_gamma(ctypes.byref(cell.c), dt, o.nb))
         if nbytes == 0:
@@ -240,9 +268,11 @@ def fock_band_density(cell: Cell, c, w, out=None, ws=None):
     (C call: fock_band_density)."""
     import torch
     dt = dtype_code(c)
+    o = orbs(c, w, cell.npw)
     if out is None:
         out = torch.empty(cell.n, dtype=torch.float64, device=c.device)
-    o = orbs(c, w)
+    if out.dtype != torch.float64 or out.device != c.device or not out.is_contiguous() or tuple(out.shape) != cell.n:
+        raise ValueError("out must be a contiguous float64 [n1, n2, n3] tensor on the orbitals' device")
     if ws is None:
         ws = band_workspace(cell, dt, o.nb, c.device)
     _check(lib().fock_band_density(ctypes.byref(cell.c), dt, ctypes.byref(o), out.data_ptr(), ws.data_ptr(),
@@ -256,13 +286,14 @@ def fock_band_force(cell: Cell, k, c, w, vloc, out=None, ws=None):
     import torch
     dt = dtype_code(c)
     rdt = torch.float64 if dt == FOCK_C128 else torch.float32
-    if vloc.dtype != rdt or not vloc.is_contiguous() or tuple(vloc.shape) != cell.n:
-        raise ValueError("vloc must be a contiguous real [n1, n2, n3] tensor in the orbitals' precision")
+    if vloc.dtype != rdt or not vloc.is_contiguous() or tuple(vloc.shape) != cell.n or vloc.device != c.device:
+        raise ValueError("vloc must be a contiguous real [n1, n2, n3] tensor in the orbitals' precision and device")
+    o = orbs(c, w, cell.npw)
     if out is None:
         out = torch.empty_like(c)
+    _like(out, c, "out")
     if out.shape != c.shape or out.stride() != c.stride():
         raise ValueError("out must have the coefficients' shape and strides")
-    o = orbs(c, w)
     if ws is None:
         ws = band_workspace(cell, dt, o.nb, c.device)
     _check(lib().fock_band_force(ctypes.byref(cell.c), _qarr(k), dt, ctypes.byref(o), vloc.data_ptr(),
@@ -298,12 +329,14 @@ def fock_apply(cell: Cell, q, c_occ, f_occ, c_tgt, out=None, ws=None):
     """(V_x psi_j) on the sphere for every target: a [n_tgt, npw] tensor (C call: fock_apply)."""
     import torch
     dt = dtype_code(c_occ)
+    _like(c_tgt, c_occ, "c_tgt")
+    if out is not None:
+        _like(out, c_occ, "out")
+    ones = torch.ones(c_tgt.shape[0], dtype=torch.float64, device=c_tgt.device)
+    o, t = orbs(c_occ, f_occ, cell.npw), orbs(c_tgt, ones, cell.npw)
     if out is None:
         out = torch.empty((c_tgt.shape[0], cell.npw), dtype=c_tgt.dtype, device=c_tgt.device)
-    ones = torch.ones(c_tgt.shape[0], dtype=torch.float64, device=c_tgt.device)
-    o, t = orbs(c_occ, f_occ), orbs(c_tgt, ones)
-    if out.shape[0] > 1 and out.stride(0) != t.ld:
-        raise ValueError("out must have the targets' leading dimension")
+    _rows(out, c_occ, "out", t.nb, cell.npw, t.ld)
     if ws is None:
         ws = workspace(cell, dt, o.nb, t.nb, c_occ.device)
     _check(lib().fock_apply(ctypes.byref(cell.c), _qarr(q), dt, ctypes.byref(o), ctypes.byref(t),
@@ -316,9 +349,12 @@ def fock_energy(cell: Cell, q, c_occ, f_occ, c_tgt, g_tgt, out=None, ws=None):
     """Exchange energy as a device float64 scalar tensor (C call: fock_energy)."""
     import torch
     dt = dtype_code(c_occ)
+    _like(c_tgt, c_occ, "c_tgt")
+    o, t = orbs(c_occ, f_occ, cell.npw), orbs(c_tgt, g_tgt, cell.npw)
     if out is None:
         out = torch.empty((), dtype=torch.float64, device=c_occ.device)
-    o, t = orbs(c_occ, f_occ), orbs(c_tgt, g_tgt)
+    if out.dtype != torch.float64 or out.device != c_occ.device or out.numel() < 1:
+        raise ValueError("out must be a float64 scalar on the coefficients' device")
     if ws is None:
         ws = workspace(cell, dt, o.nb, t.nb, c_occ.device)
     _check(lib().fock_energy(ctypes.byref(cell.c), _qarr(q), dt, ctypes.byref(o), ctypes.byref(t),
@@ -329,8 +365,16 @@ def fock_energy(cell: Cell, q, c_occ, f_occ, c_tgt, g_tgt, out=None, ws=None):
 def fock_energy_backward(cell: Cell, q, c_occ, f_occ, c_tgt, g_tgt, grad_ex, grad_occ=None, grad_tgt=None,
                          ws=None):
     """Wirtinger gradients grad_ex * dE/dconj(c) into grad_occ / grad_tgt (C call: fock_energy_backward)."""
+    import torch
     dt = dtype_code(c_occ)
-    o, t = orbs(c_occ, f_occ), orbs(c_tgt, g_tgt)
+    _like(c_tgt, c_occ, "c_tgt")
+    o, t = orbs(c_occ, f_occ, cell.npw), orbs(c_tgt, g_tgt, cell.npw)
+    if grad_ex.dtype != torch.float64 or grad_ex.device != c_occ.device or grad_ex.numel() < 1:
+        raise ValueError("grad_ex must be a float64 scalar on the coefficients' device")
+    if grad_occ is not None:
+        _rows(grad_occ, c_occ, "grad_occ", o.nb, cell.npw, o.ld)
+    if grad_tgt is not None:
+        _rows(grad_tgt, c_occ, "grad_tgt", t.nb, cell.npw, t.ld)
     if ws is None:
         ws = workspace(cell, dt, o.nb, t.nb, c_occ.device)
     _check(lib().fock_energy_backward(
@@ -371,13 +415,21 @@ def fock_trace_read(reset: bool = True) -> dict:
 # ---------------------------------------------------------------------------
 # k-point mesh
 # ---------------------------------------------------------------------------
-def _kmesh_args(kpts, C, W):
+def _kmesh_args(cell, kpts, C, W):
+    if C.dim() != 3 or W.dim() != 2 or tuple(W.shape) != tuple(C.shape[:2]):
+        raise ValueError("C must be [nk, nb, npw] and W [nk, nb]")
     nk = int(C.shape[0])
     kp = np.ascontiguousarray(np.asarray(kpts, dtype=np.float64).reshape(nk, 3))
     sets = (fock_orbs * nk)()
     for k in range(nk):
-        sets[k] = orbs(C[k], W[k])
+        sets[k] = orbs(C[k], W[k], cell.npw)
     return nk, kp, sets
+
+
+def _scalar_out(out, C, name="out"):
+    import torch
+    if out.dtype != torch.float64 or out.device != C.device or out.numel() < 1:
+        raise ValueError(f"{name} must be a float64 scalar on the coefficients' device")
 
 
 def fock_workspace_size_kmesh(cell: Cell, dtype: int, nk: int, nb_max: int) -> int:
@@ -397,9 +449,10 @@ def fock_energy_kmesh(cell: Cell, kpts, C, W, out=None, ws=None):
     weights (occupation / N_k).  Returns a device float64 scalar (C call: fock_energy_kmesh)."""
     import torch
     dt = dtype_code(C)
-    nk, kp, sets = _kmesh_args(kpts, C, W)
+    nk, kp, sets = _kmesh_args(cell, kpts, C, W)
     if out is None:
         out = torch.empty((), dtype=torch.float64, device=C.device)
+    _scalar_out(out, C)
     if ws is None:
         ws = workspace_kmesh(cell, dt, nk, int(C.shape[1]), C.device)
     _check(lib().fock_energy_kmesh(ctypes.byref(cell.c), nk, kp.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
@@ -411,7 +464,13 @@ def fock_energy_kmesh_backward(cell: Cell, kpts, C, W, grad_ex, grad, ws=None):
     """grad[k] = grad_ex * dE/dconj(C[k]) (C call: fock_energy_kmesh_backward);
     a None entry skips that k-point."""
     dt = dtype_code(C)
-    nk, kp, sets = _kmesh_args(kpts, C, W)
+    nk, kp, sets = _kmesh_args(cell, kpts, C, W)
+    _scalar_out(grad_ex, C, "grad_ex")
+    if len(grad) != nk:
+        raise ValueError("one gradient entry (or None) per k-point")
+    for k in range(nk):
+        if grad[k] is not None:
+            _rows(grad[k], C, f"grad[{k}]", sets[k].nb, cell.npw, sets[k].ld)
     ptrs = (ctypes.c_void_p * nk)(*[grad[k].data_ptr() if grad[k] is not None else None for k in range(nk)])
     if ws is None:
         ws = workspace_kmesh(cell, dt, nk, int(C.shape[1]), C.device)
@@ -427,11 +486,16 @@ def fock_energy_kmesh_grad(cell: Cell, kpts, C, W, grad=None, out=None, ws=None)
     fock_energy_kmesh_grad).  Returns (E as a device FP64 scalar, grad)."""
     import torch
     dt = dtype_code(C)
-    nk, kp, sets = _kmesh_args(kpts, C, W)
+    nk, kp, sets = _kmesh_args(cell, kpts, C, W)
     if grad is None:
         grad = torch.empty_like(C)
     if out is None:
         out = torch.empty((), dtype=torch.float64, device=C.device)
+    _scalar_out(out, C)
+    if len(grad) != nk:
+        raise ValueError("one gradient block per k-point")
+    for k in range(nk):
+        _rows(grad[k], C, f"grad[{k}]", sets[k].nb, cell.npw, sets[k].ld)
     ptrs = (ctypes.c_void_p * nk)(*[grad[k].data_ptr() for k in range(nk)])
     if ws is None:
         ws = workspace_kmesh(cell, dt, nk, int(C.shape[1]), C.device)
@@ -458,10 +522,22 @@ class BatchPlan:
             raise ValueError("one coefficient block and one weight vector per cell")
         if (tgt_coeffs is None) != (tgt_weights is None):
             raise ValueError("target coefficients and weights go together")
+        if n == 0:
+            raise ValueError("a batch needs at least one system")
         dt = dtype_code(coeffs[0])
         self.cells, self.coeffs, self.weights = list(cells), list(coeffs), list(weights)
         self.tgt_coeffs = list(tgt_coeffs) if tgt_coeffs is not None else self.coeffs
         self.tgt_weights = list(tgt_weights) if tgt_weights is not None else self.weights
+        if not (len(self.tgt_coeffs) == len(self.tgt_weights) == n):
+            raise ValueError("one target block and one target weight vector per cell")
+        if q is not None and len(q) != n:
+            raise ValueError("one q-vector per cell")
+        ref = coeffs[0]
+        for k in range(n):
+            _like(self.coeffs[k], ref, f"coeffs[{k}]")
+            _like(self.tgt_coeffs[k], ref, f"tgt_coeffs[{k}]")
+            orbs(self.coeffs[k], self.weights[k], self.cells[k].npw)
+            orbs(self.tgt_coeffs[k], self.tgt_weights[k], self.cells[k].npw)
         self.outs = [torch.empty_like(c) for c in self.tgt_coeffs]
         self.ex = torch.empty(n, dtype=torch.float64, device=coeffs[0].device)
         cs = (fock_cell * n)(*[c.c for c in self.cells])
@@ -487,6 +563,10 @@ class BatchPlan:
 
     def check(self):
         _check(lib().fock_batch_check(self._plan))
+
+    def set_wait_limit(self, ms: float):
+        """Bound on one dependency wait of the persistent kernel, in ms (<= 0: the plan's default)."""
+        _check(lib().fock_batch_set_wait_limit(self._plan, float(ms)))
 
     def info(self) -> dict:
         import json

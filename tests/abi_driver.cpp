@@ -4,9 +4,11 @@
 // each call either fails validation or stops at the device query.
 #include <cstdio>
 #include <cstring>
+#include <string>
 #include <vector>
 
 #include "fock.h"
+#include "../paper_1305_7313_amd/csrc/tune_cache.h"
 
 static int fails = 0;
 #define EXPECT(cond)                                            \
@@ -19,7 +21,7 @@ static int fails = 0;
 
 static bool reached_device_or_ok(fock_status st) { return st == FOCK_OK || st == FOCK_E_HIP; }
 
-int main() {
+int main(int argc, char** argv) {
   // cubic 10 bohr cell, 24^3 grid, sphere |m|^2 <= 25 (alias-free: |m_a| <= 5)
   std::vector<int32_t> mill;
   for (int a = -5; a <= 5; ++a)
@@ -124,6 +126,61 @@ int main() {
   EXPECT(fock_batch_plan_create(&cell, &o, nullptr, &qlat, 1, FOCK_C128, nullptr, &plan) == FOCK_E_SINGULAR_Q);
   EXPECT(plan == nullptr);
   EXPECT(fock_batch_apply(nullptr, nullptr, nullptr, nullptr) == FOCK_E_ARG);
+
+  EXPECT(fock_batch_set_wait_limit(nullptr, 1.0) == FOCK_E_ARG);
+
+  // tune cache: entries outside the schedule's ranges are ignored (the batch is tuned again)
+  {
+    const std::string cache = std::string(argc > 1 ? argv[1] : ".") + "/abi_driver_tune_cache.json";
+    const char* path = cache.c_str();
+    if (FILE* f = std::fopen(path, "w")) {
+      std::fprintf(f,
+                   "{\n"
+                   "\"ok\": {\"tile\": 8, \"slots\": 6, \"units_per_ticket\": 32, \"blocks_per_cu\": 2, \"ms\": 1.5, \"mode\": 0},\n"
+                   "\"old\": {\"tile\": 16, \"slots\": 4, \"units_per_ticket\": 128, \"blocks_per_cu\": 1, \"ms\": 2.0}\n"
+                   "\"slots9\": {\"tile\": 16, \"slots\": 9, \"units_per_ticket\": 32, \"blocks_per_cu\": 1, \"ms\": 1, \"mode\": 0},\n"
+                   "\"slots0\": {\"tile\": 16, \"slots\": 0, \"units_per_ticket\": 32, \"blocks_per_cu\": 1, \"ms\": 1, \"mode\": 0},\n"
+                   "\"slots3\": {\"tile\": 16, \"slots\": 3, \"units_per_ticket\": 32, \"blocks_per_cu\": 1, \"ms\": 1, \"mode\": 0},\n"
+                   "\"tile32\": {\"tile\": 32, \"slots\": 6, \"units_per_ticket\": 32, \"blocks_per_cu\": 1, \"ms\": 1, \"mode\": 0},\n"
+                   "\"ticket0\": {\"tile\": 16, \"slots\": 6, \"units_per_ticket\": 0, \"blocks_per_cu\": 1, \"ms\": 1, \"mode\": 1},\n"
+                   "\"ticketneg\": {\"tile\": 16, \"slots\": 6, \"units_per_ticket\": -4, \"blocks_per_cu\": 1, \"ms\": 1, \"mode\": 1},\n"
+                   "\"mode7\": {\"tile\": 16, \"slots\": 6, \"units_per_ticket\": 32, \"blocks_per_cu\": 1, \"ms\": 1, \"mode\": 7},\n"
+                   "\"bpc0\": {\"tile\": 16, \"slots\": 6, \"units_per_ticket\": 32, \"blocks_per_cu\": 0, \"ms\": 1, \"mode\": 0},\n"
+                   "\"nanms\": {\"tile\": 16, \"slots\": 6, \"units_per_ticket\": 32, \"blocks_per_cu\": 1, \"ms\": nan, \"mode\": 0},\n"
+                   "\"short\": {\"tile\": 16, \"slots\": 6},\n"
+                   "\"junk\": {garbage},\n"
+                   "\"twice\": {\"tile\": 8, \"slots\": 6, \"units_per_ticket\": 32, \"blocks_per_cu\": 1, \"ms\": 1, \"mode\": 0},\n"
+                   "\"twice\": {\"tile\": 99, \"slots\": 6, \"units_per_ticket\": 32, \"blocks_per_cu\": 1, \"ms\": 1, \"mode\": 0}\n"
+                   "}\n");
+      std::fclose(f);
+    }
+    fockx::BatchParams p;
+    EXPECT(fockx::tune_cache_lookup(path, "ok", &p) && p.tile == 8 && p.units_per_ticket == 32 &&
+           p.blocks_per_cu == 2 && p.mode == 0);
+    EXPECT(fockx::tune_cache_lookup(path, "old", &p) && p.slots == 4 && p.mode == 0);
+    for (const char* bad : {"slots9", "slots0", "slots3", "tile32", "ticket0", "ticketneg", "mode7", "bpc0", "nanms",
+                            "short", "junk", "twice", "absent"}) {
+      fockx::BatchParams q;
+      const bool got = fockx::tune_cache_lookup(path, bad, &q);
+      if (got) std::printf("accepted malformed cache entry %s\n", bad);
+      EXPECT(!got);
+    }
+    EXPECT(!fockx::tune_cache_lookup("", "ok", &p));
+    EXPECT(!fockx::tune_cache_lookup("no/such/dir/cache.json", "ok", &p));
+    // a stored entry reads back; an out-of-range one is never written
+    fockx::BatchParams w;
+    w.tile = 16;
+    w.units_per_ticket = 512;
+    w.mode = 1;
+    w.ms = 12.5;
+    fockx::tune_cache_store(path, "new", w);
+    EXPECT(fockx::tune_cache_lookup(path, "new", &p) && p.units_per_ticket == 512 && p.mode == 1);
+    EXPECT(fockx::tune_cache_lookup(path, "ok", &p) && p.tile == 8);
+    w.slots = 40;
+    fockx::tune_cache_store(path, "bad_store", w);
+    EXPECT(!fockx::tune_cache_lookup(path, "bad_store", &p));
+    std::remove(path);
+  }
 
   // transforms and strings
   const int32_t grid[3] = {24, 24, 24};

@@ -1,6 +1,7 @@
 """The C entry points' host code under AddressSanitizer and
 UndefinedBehaviorSanitizer (CPU only): tests/abi_driver.cpp exercises every
-call's validation, error codes, workspace sizes and the exchange-grid rule.
+call's validation, error codes, workspace sizes and the exchange-grid rule,
+and the batch tune cache's handling of malformed entries.
 capi.cpp and the driver are compiled with the sanitizers on the host side;
 the kernel objects of the regular build are linked unchanged."""
 import os
@@ -34,7 +35,7 @@ def test_abi_host_code_is_clean_under_sanitizers(tmp_path):
                        capture_output=True, text=True)
     assert r.returncode == 0, r.stderr[-4000:]
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=0", UBSAN_OPTIONS="print_stacktrace=1")
-    r = subprocess.run([exe], capture_output=True, text=True, env=env, timeout=300)
+    r = subprocess.run([exe, str(tmp_path)], capture_output=True, text=True, env=env, timeout=300)
     out = r.stdout + r.stderr
     assert r.returncode == 0, out[-4000:]
     assert "runtime error" not in out and "AddressSanitizer" not in out, out[-4000:]
