@@ -27,6 +27,9 @@ def _workload(name):
         elif name == "c5":
             s, kpts, orbs = synth.config5()
             _CACHE[name] = (s, dict(enumerate(orbs)), dict(enumerate(kpts)))
+        elif name.startswith("c4:"):
+            s, c = synth.config4_system(int(name[3:]))
+            _CACHE[name] = (s, {0: c}, {0: np.zeros(3)})
         else:
             raise KeyError(name)
     return _CACHE[name]
@@ -91,6 +94,16 @@ def oracle_apply(name, targets, n_occ, chunk, kt=0, ko=0, weight=1.0, k0=0.0):
     tasks = [(name, kt, ko, list(targets), lo, min(lo + chunk, n_occ), weight, k0)
              for lo in range(0, n_occ, chunk)]
     return sum(_run(_apply_task, tasks, f"{name} apply"))
+
+
+def oracle_kmesh_grad_rows(name, kt, targets, n_occ, chunk, nk, weight, k0):
+    """Oracle dE/dconj(c_jk) for the listed targets j at k = kt of a k-mesh
+    energy with equal weights: weight * sum_k' (V_x psi_jk) with the occupied
+    set k' and q = k - k' (both blocks (k, k') and (k', k) contribute half),
+    K(0) = k0 only in the block k' = k."""
+    tasks = [(name, kt, ko, list(targets), lo, min(lo + chunk, n_occ), weight, k0 if ko == kt else 0.0)
+             for ko in range(nk) for lo in range(0, n_occ, chunk)]
+    return weight * sum(_run(_apply_task, tasks, f"{name} gradient rows k={kt}"))
 
 
 def oracle_energy(name, n_tgt, n_occ, chunk, kt=0, ko=0, weight=1.0, k0=0.0):

@@ -120,7 +120,51 @@ def test_batch_config4_fp32(mode, monkeypatch):
     err = rel_fro(host(plan.outs[k]), ref)
     report("config4", batched_vs_single_worst=worst, smallest_system_vs_oracle=err)
     assert worst < 1e-6 and err < 1e-5
+    # oracle on one system of each large grid: rows {0, middle, last} against every occupied orbital
+    outs = [host(o).astype(np.complex128) for o in plan.outs]
     plan.close()
+    for k, (rows, ref) in _config4_oracle_rows().items():
+        v = outs[k][rows]
+        e1, e2 = rel_fro(v, ref), max_row_rel(v, ref)
+        report(f"config4 FP32 batched mode {mode} system {k} ({grids[k]}^3, {nbs[k]} orbitals) rows {rows}",
+               vs_oracle=e1, vs_oracle_maxband=e2)
+        assert e1 < 1e-5 and e2 < 1e-5
+
+
+# one system of each large grid of the 16-system workload: 96^3 (system 0),
+# 72^3 (system 1), 64^3 (system 3)
+_C4_ORACLE_SYSTEMS = (0, 1, 3)
+_C4_ORACLE = {}
+
+
+def _config4_oracle_rows():
+    """Oracle (V_x psi_j) for rows {0, middle, last} of systems 0, 1 and 3 of
+    the 16-system workload, each against all of its occupied orbitals."""
+    from tests import oracle_pool
+    if not _C4_ORACLE:
+        _, nbs = synth.config4_layout()
+        for k in _C4_ORACLE_SYSTEMS:
+            nb = int(nbs[k])
+            rows = [0, nb // 2, nb - 1]
+            _C4_ORACLE[k] = (rows, oracle_pool.oracle_apply(f"c4:{k}", rows, nb, 16))
+    return _C4_ORACLE
+
+
+def test_config4_fp64_single_vs_oracle():
+    """The FP64 single-system path on the large grids of the 16-system
+    workload, rows against the oracle at the FP64 tolerance."""
+    import torch
+    F = _F()
+    for k, (rows, ref) in _config4_oracle_rows().items():
+        s, c = synth.config4_system(k)
+        cell = F.Cell(s.a, s.n, s.miller)
+        C = torch.from_numpy(c).cuda()
+        f = torch.ones(c.shape[0], dtype=torch.float64, device="cuda")
+        print(f"[case] config4 FP64 system {k} ({s.n[0]}^3, {c.shape[0]} orbitals)", flush=True)
+        v = host(F.fock_apply(cell, (0, 0, 0), C, f, C))[rows]
+        e1, e2 = rel_fro(v, ref), max_row_rel(v, ref)
+        report(f"config4 FP64 system {k} rows {rows}", vs_oracle=e1, vs_oracle_maxband=e2)
+        assert e1 < 1e-10 and e2 < 1e-10
 
 
 @pytest.mark.parametrize("prec", ["c128", "c64"])
@@ -168,4 +212,45 @@ def test_batch_general_systems(prec, tmp_path):
             e3 = abs(ex[k] - refs[k][1]) / abs(refs[k][1])
             report(f"batch general {prec} system {k} replay {rep}", vs_oracle=e1, vs_single=e2, E_rel=e3)
             assert e1 < tol and e2 < 1e-12 and e3 < tol
+    plan.close()
+
+
+def test_batch_wait_bound_aborts_and_recovers(monkeypatch):
+    """Failure detection of the persistent schedule, forced from the host: with
+    a bound of 10 ns on a dependency wait every wait gives up, the launch
+    drains (every block stops taking work), fock_batch_check reports
+    FOCK_E_HIP, and the next replay with the plan's own bound is correct
+    again.  512 units per ticket put dependent units in the first wave of
+    tickets, next to the units they depend on, so waits certainly occur."""
+    import torch
+    F = _F()
+    monkeypatch.setenv("FOCK_BATCH_MODE", "0")
+    monkeypatch.setenv("FOCK_BATCH_TUNE", "0")
+    monkeypatch.setenv("FOCK_BATCH_TICKET", "512")
+    systems = _small_batch()
+    cells, C, W = [], [], []
+    for s, c, f, gb in systems:
+        cells.append(F.Cell(s.a, s.n, s.miller, g0=gb, gb_alpha=0.6, nq=(2, 2, 2)))
+        C.append(torch.from_numpy(c).to(torch.complex64).cuda())
+        W.append(torch.from_numpy(f).cuda())
+    print("[case] batch wait bound: create", flush=True)
+    plan = F.BatchPlan(cells, C, W)
+    info = plan.info()
+    assert info["mode"] == "persistent" and info["units_per_ticket"] == 512
+    plan.apply()
+    plan.check()
+    ref = [host(o).copy() for o in plan.outs]
+    print("[case] batch wait bound: replay with a 10 ns bound", flush=True)
+    plan.set_wait_limit(1e-5)
+    plan.apply()
+    with pytest.raises(F.FockError) as err:
+        plan.check()
+    assert err.value.status == F.FOCK_E_HIP and "aborted" in str(err.value)
+    print("[case] batch wait bound: replay with the plan's bound", flush=True)
+    plan.set_wait_limit(0.0)
+    plan.apply()
+    plan.check()
+    for k in range(len(systems)):
+        assert np.array_equal(host(plan.outs[k]), ref[k]), k
+    report("batch wait bound", aborted_then_recovered=1)
     plan.close()
