@@ -129,7 +129,7 @@ static_assert(compact_slots_ok(), "compact diagonal-tile slot maps");
 struct PencilArgs {
   const signed char* live;  // pair buffers: last live row per plane column (see PlaneArgs), or null
   void* x;             // [npairs or nb][N]
-  double* epart;       // energy partials [ngroups][npairs] (group-major) or null
+  double* epart;       // PENCIL_FE: energy partials [ngroups][npairs] (group-major)
   const void* tw1;     // twiddle table, length n1
   KernelParams kp;
   long long N;
@@ -590,6 +590,8 @@ __device__ __forceinline__ void pencil_body(const PencilArgs& A, int lid, unsign
     return;
   } else {
     // Coulomb kernel on the natural-order outputs (column c0 + b, k1 = row).
+    // PENCIL_FE only sums the FP64 energy partials; PENCIL_FKI only scales.
+    constexpr bool energy = MODE == PENCIL_FE;
     const KernelParams& kp = A.kp;
     double esum = 0.0;
     const double k0 = kp.q_zero ? *kp.k0 : 0.0;
@@ -620,7 +622,8 @@ __device__ __forceinline__ void pencil_body(const PencilArgs& A, int lid, unsign
           const float y0 = float(gy) + float(m1) * float(kp.b[0][1]);
           const float z0 = float(gz) + float(m1) * float(kp.b[0][2]);
           const float g2 = x0 * x0 + y0 * y0 + z0 * z0;
-          float kk = float(kFourPi) / g2;
+          // hardware reciprocal (1 ulp): far inside the FP32 path's error budget
+          float kk = float(kFourPi) * __builtin_amdgcn_rcpf(g2);
           if (kp.ecut > 0.0) {
             const double dx = gx + m1 * kp.b[0][0], dy = gy + m1 * kp.b[0][1], dz = gz + m1 * kp.b[0][2];
             if (dx * dx + dy * dy + dz * dz > kp.ecut) kk = 0.0f;
@@ -629,11 +632,14 @@ __device__ __forceinline__ void pencil_body(const PencilArgs& A, int lid, unsign
           kv = kk;
         }
         cx<T>& z = v[s * P1::R + r];
-        if (act) esum += double(kv * (z.x * z.x + z.y * z.y));
-        z = cscale<T>(z, kv);
+        if constexpr (energy) {
+          if (act) esum += double(kv * (z.x * z.x + z.y * z.y));
+        } else {
+          z = cscale<T>(z, kv);
+        }
       }
     }
-    if (A.epart) {
+    if constexpr (energy) {
       const double tot = block_sum(esum, red);
       if (t == 0) A.epart[(long long)g * A.count + pr] = tot;
     }
