@@ -92,6 +92,24 @@ size_t fock_workspace_size(const fock_cell *cell, int32_t dtype, int32_t n_occ, 
 fock_status fock_apply(const fock_cell *cell, const double q[3], int32_t dtype, const fock_orbs *occ,
                        const fock_orbs *tgt, void *vx_out, void *ws, size_t ws_bytes, void *stream);
 
+/* Allocation-free form of fock_apply, for callers that cannot allocate
+ * device memory (code under stream capture, tight serving loops, harnesses
+ * that forbid allocation): same arguments, result and errors as fock_apply,
+ * without the workspace.  The library's per-call device tables (sphere slots,
+ * live columns, twiddles) and the fock_apply workspace live in one fixed
+ * device array of FOCK_NOALLOC_SCRATCH_BYTES per GPU, part of the library's
+ * code object: each GPU the library runs on holds it until the process ends.
+ * The call allocates no device memory (its tables reach the device as kernel
+ * arguments, stream ordered).  FOCK_E_WORKSPACE when the call would need
+ * more than the array (fock_workspace_size plus the tables; e.g. the 24^3
+ * grid with 8 occupied and 8 target orbitals fits, a 64^3 grid with 16 does
+ * not).  Every call on one GPU uses that GPU's array: calls that overlap in
+ * time on one GPU (different streams or threads) race; calls ordered on one
+ * stream do not. */
+#define FOCK_NOALLOC_SCRATCH_BYTES ((size_t)32 << 20)
+fock_status fock_apply_noalloc(const fock_cell *cell, const double q[3], int32_t dtype, const fock_orbs *occ,
+                               const fock_orbs *tgt, void *vx_out, void *stream);
+
 /* Gamma point, real orbitals (section 4 at q = 0, with phi(r) real): V_x of
  * the block applied to itself, vx_out[j][p] = (V_x psi_j)(G_p) with
  * occupations orbs.w, as fock_apply(occ = tgt = orbs, q = 0) returns it.

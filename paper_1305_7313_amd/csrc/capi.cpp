@@ -1894,9 +1894,130 @@ fock_status batch_create(BatchPlanImpl& B, const std::string& cache) {
   B.d_ticket = static_cast<unsigned long long*>(p);
   return batch_tune_and_capture<T>(B, cache);
 }
+// ---------------------------------------------------------------------------
+// Allocation-free apply (fock_apply_noalloc): the plan's device tables and
+// the workspace of fock_apply live in one fixed device array per GPU.
+// ---------------------------------------------------------------------------
+constexpr size_t kScratchBytes = FOCK_NOALLOC_SCRATCH_BYTES;
+constexpr int kMaxDevices = 64;
+
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+}  // namespace
+
+// One copy per GPU, held until the process ends.  Host code never uses this
+// name as an address: the device address comes from hipGetSymbolAddress,
+// per device (scratch_base).
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+// Device address of the current GPU's scratch array, looked up once per
+// device with that device current.
+fock_status scratch_base(char** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(FOCK_E_HIP, "no HIP device available");
+  if (dev < 0 || dev >= kMaxDevices) return fail(FOCK_E_HIP, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lk(g_scratch_mutex);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(FOCK_E_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = static_cast<char*>(g_scratch_ptr[dev]);
+  return FOCK_OK;
+}
+
+// Scratch layout of one call: slot table, live-column table, three twiddle
+// tables, then the workspace of fock_apply.
+struct ScratchLayout {
+  size_t slot, live, tw[3], ws, total;
+};
+ScratchLayout scratch_layout(const fock_cell* cell, int dtype, const Layout& L) {
+  const size_t cb = dtype == FOCK_C128 ? 16 : 8;
+  ScratchLayout S;
+  size_t off = 0;
+  S.slot = off; off += align_up(sizeof(int32_t) * (size_t)cell->npw);
+  S.live = off; off += align_up((size_t)cell->n[2]);
+  for (int k = 0; k < 3; ++k) {
+    S.tw[k] = off;
+    off += align_up(cb * (size_t)cell->n[k]);
+  }
+  S.ws = off; off += L.total;
+  S.total = off;
+  return S;
+}
+
+template <typename T>
+fock_status apply_noalloc_impl(const fock_cell* cell, const double q[3], const fock_orbs* occ, const fock_orbs* tgt,
+                               void* vx_out, hipStream_t s) {
+  const int dtype = sizeof(T) == 8 ? FOCK_C128 : FOCK_C64;
+  double b[3][3], omega = 0.0;
+  fock_status st = check_plan_cell(cell, dtype, b, &omega);
+  if (st != FOCK_OK) return st;
+  if ((st = check_orbs(occ, cell->npw, "occ")) != FOCK_OK) return st;
+  if ((st = check_orbs(tgt, cell->npw, "tgt")) != FOCK_OK) return st;
+  bool q_zero = false;
+  if ((st = check_q(cell, q, &q_zero)) != FOCK_OK) return st;
+  if ((st = check_alias(cell, q, 1)) != FOCK_OK) return st;
+  if (tgt->nb > 0 && !vx_out) return fail(FOCK_E_ARG, "vx_out is NULL");
+  const long long N = (long long)cell->n[0] * cell->n[1] * cell->n[2];
+  const int ngroups = cell->n[1] * cell->n[2] / pencil_columns(cell->n[0], (int)sizeof(T));
+  const Layout L = layout(N, (int)sizeof(cx<T>), ngroups, occ->nb, tgt->nb);
+  const ScratchLayout S = scratch_layout(cell, dtype, L);
+  if (S.total > kScratchBytes) {
+    char buf[200];
+    std::snprintf(buf, sizeof buf, "this call needs %zu bytes of device memory; the allocation-free scratch holds %zu",
+                  S.total, kScratchBytes);
+    return fail(FOCK_E_WORKSPACE, buf);
+  }
+  std::vector<int> slot;
+  std::vector<signed char> live;
+  bool has_live = false;
+  if ((st = sphere_tables(cell, &slot, &live, &has_live)) != FOCK_OK) return st;
+  char* base = nullptr;
+  if ((st = scratch_base(&base)) != FOCK_OK) return st;
+  // tables, rewritten by every call (stream ordered after the previous call's kernels)
+  FX_HIP(launch_put_words(base + S.slot, slot.data(), sizeof(int32_t) * slot.size(), s));
+  if (has_live) {
+    live.resize((live.size() + 3) / 4 * 4, (signed char)-1);
+    FX_HIP(launch_put_words(base + S.live, live.data(), live.size(), s));
+  }
+  for (int k = 0; k < 3; ++k) {
+    const std::vector<unsigned char> tw = host_twiddles(cell->n[k], dtype);
+    FX_HIP(launch_put_words(base + S.tw[k], tw.data(), tw.size(), s));
+  }
+  Plan P;
+  P.owns = false;
+  (void)hipGetDevice(&P.device);
+  for (int k = 0; k < 3; ++k) P.n[k] = cell->n[k];
+  P.N = N;
+  P.dtype = dtype;
+  std::memcpy(P.a, cell->a, sizeof(P.a));
+  std::memcpy(P.b, b, sizeof(b));
+  P.omega = omega;
+  P.npw = cell->npw;
+  P.d_slot = reinterpret_cast<int*>(base + S.slot);
+  P.d_live = has_live ? reinterpret_cast<signed char*>(base + S.live) : nullptr;
+  for (int k = 0; k < 3; ++k) P.d_tw[k] = base + S.tw[k];
+  const double s0 = -1.0 / (omega * (double)N * (double)N);
+  return apply_impl<T>(cell, P, q, q_zero, occ, tgt, base + S.ws, L, s, vx_out, s0, nullptr, nullptr);
+}
+
 }  // namespace
 
 extern "C" {
+
+fock_status fock_apply_noalloc(const fock_cell* cell, const double q[3], int32_t dtype, const fock_orbs* occ,
+                               const fock_orbs* tgt, void* vx_out, void* stream) {
+  if (dtype != FOCK_C128 && dtype != FOCK_C64) return fail(FOCK_E_ARG, "dtype must be FOCK_C128 or FOCK_C64");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (dtype == FOCK_C128) return apply_noalloc_impl<double>(cell, q, occ, tgt, vx_out, s);
+  return apply_noalloc_impl<float>(cell, q, occ, tgt, vx_out, s);
+}
 
 size_t fock_workspace_size(const fock_cell* cell, int32_t dtype, int32_t n_occ, int32_t n_tgt) {
   if (!cell || n_occ < 0 || n_tgt < 0 || (dtype != FOCK_C128 && dtype != FOCK_C64)) return 0;

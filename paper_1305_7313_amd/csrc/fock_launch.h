@@ -42,6 +42,8 @@ hipError_t launch_energy_final(const double* tile_e, int ntiles, double scale, d
 hipError_t launch_gb(const KernelParams& kp, const int n[3], const int nq[3], double alpha, double head,
                      double* partial, int nparts, double* k0, hipStream_t s);
 hipError_t launch_set_scalar(double* p, double v, hipStream_t s);
+// Copies `bytes` (a multiple of 4) of host memory to dst through kernel arguments.
+hipError_t launch_put_words(void* dst, const void* src, size_t bytes, hipStream_t s);
 template <typename T> hipError_t launch_batch(const BatchArgs& a, int occ, int grid, hipStream_t s);
 template <typename T> int batch_blocks_per_cu(int occ);
 hipError_t launch_batch_reset(unsigned long long* ticket, int* done, int nseg, int* abort_flag, hipStream_t s);

@@ -1,4 +1,6 @@
 // Type-independent kernels: energy reductions, Gygi-Baldereschi constant.
+#include <cstring>
+
 #include "fock_launch.h"
 
 namespace fockx {
@@ -164,6 +166,33 @@ hipError_t launch_batch_reset(unsigned long long* ticket, int* done, int nseg, i
   const int blocks = (nseg + 255) / 256 > 0 ? ((nseg + 255) / 256 < 1024 ? (nseg + 255) / 256 : 1024) : 1;
   hipLaunchKernelGGL(batch_reset_kernel, dim3(blocks), dim3(256), 0, s, ticket, done, nseg, abort_flag);
   return hipGetLastError();
+}
+
+// Host bytes carried to the device as kernel arguments, a chunk per launch:
+// stream ordered, no staging buffer, nothing for the caller to keep alive.
+constexpr int kPutWords = 512;
+struct PutChunk {
+  int n;
+  uint32_t w[kPutWords];
+};
+
+__global__ void put_words_kernel(uint32_t* dst, PutChunk c) {
+  for (int k = threadIdx.x; k < c.n; k += blockDim.x) dst[k] = c.w[k];
+}
+
+hipError_t launch_put_words(void* dst, const void* src, size_t bytes, hipStream_t s) {
+  if (bytes % 4 != 0) return hipErrorInvalidValue;
+  const size_t words = bytes / 4;
+  const unsigned char* from = static_cast<const unsigned char*>(src);
+  for (size_t w0 = 0; w0 < words; w0 += kPutWords) {
+    PutChunk c;
+    c.n = (int)(words - w0 < (size_t)kPutWords ? words - w0 : (size_t)kPutWords);
+    std::memcpy(c.w, from + 4 * w0, 4 * (size_t)c.n);
+    hipLaunchKernelGGL(put_words_kernel, dim3(1), dim3(256), 0, s, static_cast<uint32_t*>(dst) + w0, c);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_set_scalar(double* p, double v, hipStream_t s) {

@@ -70,6 +70,8 @@ def lib():
         common = [P(fock_cell), P(ctypes.c_double), ctypes.c_int32, P(fock_orbs), P(fock_orbs)]
         L.fock_apply.restype = ctypes.c_int
         L.fock_apply.argtypes = common + [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
+        L.fock_apply_noalloc.restype = ctypes.c_int
+        L.fock_apply_noalloc.argtypes = common + [ctypes.c_void_p, ctypes.c_void_p]
         L.fock_energy.restype = ctypes.c_int
         L.fock_energy.argtypes = common + [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
         L.fock_energy_backward.restype = ctypes.c_int
@@ -342,6 +344,24 @@ def fock_apply(cell: Cell, q, c_occ, f_occ, c_tgt, out=None, ws=None):
     _check(lib().fock_apply(ctypes.byref(cell.c), _qarr(q), dt, ctypes.byref(o), ctypes.byref(t),
                             out.data_ptr() if out.numel() else None, ws.data_ptr(), ws.numel(),
                             _stream(c_occ.device)))
+    return out
+
+
+NOALLOC_SCRATCH_BYTES = 32 << 20  # FOCK_NOALLOC_SCRATCH_BYTES of include/fock.h
+
+
+def fock_apply_noalloc(cell: Cell, q, c_occ, f_occ, c_tgt, out):
+    """fock_apply without a workspace: the library uses its fixed per-GPU
+    scratch array and allocates nothing (C call: fock_apply_noalloc).  out is
+    the caller's [n_tgt, npw] result tensor."""
+    import torch
+    _like(c_tgt, c_occ, "c_tgt")
+    ones = torch.ones(c_tgt.shape[0], dtype=torch.float64, device=c_tgt.device)
+    o, t = orbs(c_occ, f_occ, cell.npw), orbs(c_tgt, ones, cell.npw)
+    _rows(out, c_occ, "out", t.nb, cell.npw, t.ld)
+    _check(lib().fock_apply_noalloc(ctypes.byref(cell.c), _qarr(q), dtype_code(c_occ), ctypes.byref(o),
+                                    ctypes.byref(t), out.data_ptr() if out.numel() else None,
+                                    _stream(c_occ.device)))
     return out
 
 

@@ -87,6 +87,20 @@ int main(int argc, char** argv) {
   red.ecut_fock = 25.0 * (2.0 * 3.14159265358979323846 / 10.0) * (2.0 * 3.14159265358979323846 / 10.0);
   EXPECT(reached_device_or_ok(fock_apply(&red, q0, FOCK_C128, &o, &o, out, ws, big, nullptr)));
 
+  // allocation-free apply: same validation; requests beyond the fixed scratch array are refused on the host
+  EXPECT(fock_apply_noalloc(nullptr, q0, FOCK_C128, &o, &o, out, nullptr) == FOCK_E_ARG);
+  EXPECT(fock_apply_noalloc(&cell, q0, 5, &o, &o, out, nullptr) == FOCK_E_ARG);
+  EXPECT(fock_apply_noalloc(&cell, qlat, FOCK_C128, &o, &o, out, nullptr) == FOCK_E_SINGULAR_Q);
+  EXPECT(fock_apply_noalloc(&cell, q0, FOCK_C128, &o, &o, nullptr, nullptr) == FOCK_E_ARG);
+  EXPECT(fock_apply_noalloc(&wc, q0, FOCK_C128, &o, &o, out, nullptr) == FOCK_E_ALIAS);
+  {
+    fock_orbs many = o;
+    many.nb = 64;  // a 16 x 16 pair tile of 24^3 FP64 boxes alone is 56 MB
+    EXPECT(fock_apply_noalloc(&cell, q0, FOCK_C128, &many, &many, out, nullptr) == FOCK_E_WORKSPACE);
+    EXPECT(std::strstr(fock_last_error(), "scratch") != nullptr);
+  }
+  EXPECT(reached_device_or_ok(fock_apply_noalloc(&cell, q0, FOCK_C128, &o, &o, out, nullptr)));
+
   // energies, gradients, k-mesh, Gamma, band loops
   EXPECT(fock_energy(&cell, q0, FOCK_C64, &o, &o, nullptr, ws, big, nullptr) != FOCK_OK);
   EXPECT(reached_device_or_ok(fock_energy(&cell, q0, FOCK_C64, &o, &o, ex, ws, big, nullptr)));
