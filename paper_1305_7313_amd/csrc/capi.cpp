@@ -1430,8 +1430,14 @@ struct BatchPlanImpl {
   long long total_units = 0;
   long long pairs = 0;
   BatchParams prm;
-  void* kws = nullptr;      // mode 1: workspace of the largest system's schedule
-  size_t kws_bytes = 0;
+  const char* prm_source = "default";  // how prm was chosen: default, tuned now, or read from the tune cache
+  // mode 1: the systems are split over `branches` independent graph branches
+  // (each its own stream while capturing), each with a workspace sized for
+  // its largest system
+  std::vector<void*> kws;
+  std::vector<size_t> kws_bytes;
+  std::vector<hipStream_t> branch_streams;  // capture streams of branches 1.. (branch 0: cap)
+  std::vector<hipEvent_t> branch_events;    // fork and join events (no timing)
   hipStream_t cap = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -1441,6 +1447,8 @@ struct BatchPlanImpl {
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
     for (void* p : allocs) (void)hipFree(p);
+    for (hipEvent_t e : branch_events) (void)hipEventDestroy(e);
+    for (hipStream_t st : branch_streams) (void)hipStreamDestroy(st);
     if (cap) (void)hipStreamDestroy(cap);
   }
   fock_status alloc(void** p, size_t bytes) {
@@ -1606,15 +1614,55 @@ fock_status batch_capture(BatchPlanImpl& B, const BatchParams& prm) {
     bpc = prm.blocks_per_cu > 0 && prm.blocks_per_cu < bpc_max ? prm.blocks_per_cu : bpc_max;
     grid = bpc * B.cus;
   }
-  if (prm.mode == 1 && !B.kws) {
-    size_t need = 0;
+  std::vector<int> branch_of;
+  if (prm.mode == 1) {
+    // systems to branches: longest first onto the least loaded branch, the
+    // load of a system taken as its pairs times N log N
+    const int nbr = std::max(1, std::min(prm.branches, B.nsys));
+    std::vector<int> order(B.nsys);
+    std::vector<double> cost(B.nsys), load(nbr, 0.0);
+    for (int k = 0; k < B.nsys; ++k) {
+      order[k] = k;
+      const double N = (double)B.plans[k]->N;
+      cost[k] = (double)B.orbs[k].nb * (double)B.tgt[k].nb * N * std::log2(N);
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+    branch_of.assign(B.nsys, 0);
+    for (int k : order) {
+      const int b = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      branch_of[k] = b;
+      load[b] += cost[k];
+    }
+    // one workspace per branch, sized for its largest system (kept across captures)
+    std::vector<size_t> need(nbr, 0);
     for (int k = 0; k < B.nsys; ++k) {
       const Plan& P = *B.plans[k];
       const int ng = P.n[1] * P.n[2] / pencil_columns(P.n[0], (int)sizeof(T));
-      need = std::max(need, layout(P.N, (int)sizeof(cx<T>), ng, B.orbs[k].nb, B.tgt[k].nb).total);
+      need[branch_of[k]] = std::max(need[branch_of[k]], layout(P.N, (int)sizeof(cx<T>), ng, B.orbs[k].nb,
+                                                                B.tgt[k].nb).total);
     }
-    if ((st = B.alloc(&B.kws, need)) != FOCK_OK) return st;
-    B.kws_bytes = need;
+    for (int b = 0; b < nbr; ++b) {
+      if ((int)B.kws.size() <= b) {
+        B.kws.push_back(nullptr);
+        B.kws_bytes.push_back(0);
+      }
+      if (B.kws_bytes[b] < need[b]) {
+        void* p = nullptr;
+        if ((st = B.alloc(&p, need[b])) != FOCK_OK) return st;
+        B.kws[b] = p;
+        B.kws_bytes[b] = need[b];
+      }
+    }
+    while ((int)B.branch_streams.size() < nbr - 1) {
+      hipStream_t bs = nullptr;
+      FX_HIP(hipStreamCreateWithFlags(&bs, hipStreamNonBlocking));
+      B.branch_streams.push_back(bs);
+    }
+    while ((int)B.branch_events.size() < nbr) {
+      hipEvent_t ev = nullptr;
+      FX_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+      B.branch_events.push_back(ev);
+    }
   }
   // capture; tracing events must not enter the graph
   Tracer& TR = tracer();
@@ -1623,16 +1671,30 @@ fock_status batch_capture(BatchPlanImpl& B, const BatchParams& prm) {
   hipStream_t s = B.cap;
   auto body = [&]() -> fock_status {
     if (prm.mode == 1) {
-      // each system's own per-shape schedule (the single-system path), in turn
+      // each system's own per-shape schedule (the single-system path); the
+      // systems of one branch in turn, the branches forked from and joined
+      // back into the capture stream (independent paths of the graph)
+      const int nbr = (int)std::min(B.kws.size(), (size_t)std::max(1, std::min(prm.branches, B.nsys)));
+      std::vector<hipStream_t> bst(nbr, s);
+      for (int b = 1; b < nbr; ++b) bst[b] = B.branch_streams[b - 1];
+      if (nbr > 1) {
+        FX_HIP(hipEventRecord(B.branch_events[0], s));
+        for (int b = 1; b < nbr; ++b) FX_HIP(hipStreamWaitEvent(bst[b], B.branch_events[0], 0));
+      }
       for (int k = 0; k < B.nsys; ++k) {
         const Plan& P = *B.plans[k];
+        const int b = branch_of[k];
         const int ng = P.n[1] * P.n[2] / pencil_columns(P.n[0], (int)sizeof(T));
         const Layout L = layout(P.N, (int)sizeof(cx<T>), ng, B.orbs[k].nb, B.tgt[k].nb);
-        if (L.total > B.kws_bytes) return fail(FOCK_E_WORKSPACE, "batch workspace too small");
+        if (L.total > B.kws_bytes[b]) return fail(FOCK_E_WORKSPACE, "batch workspace too small");
         const double s0 = -1.0 / (P.omega * (double)P.N * (double)P.N);
         fock_status st2 = apply_impl<T>(&B.cells[k], P, &B.q[3 * k], B.qzero[k] != 0, &B.orbs[k], &B.tgt[k],
-                                        static_cast<char*>(B.kws), L, s, B.outs[k], s0, nullptr, nullptr);
+                                        static_cast<char*>(B.kws[b]), L, bst[b], B.outs[k], s0, nullptr, nullptr);
         if (st2 != FOCK_OK) return st2;
+      }
+      for (int b = 1; b < nbr; ++b) {
+        FX_HIP(hipEventRecord(B.branch_events[b], bst[b]));
+        FX_HIP(hipStreamWaitEvent(s, B.branch_events[b], 0));
       }
       return batch_energies<T>(B, s);
     }
@@ -1672,14 +1734,16 @@ fock_status batch_capture(BatchPlanImpl& B, const BatchParams& prm) {
   FX_HIP(hipGraphInstantiate(&B.exec, B.graph, nullptr, nullptr, 0));
   char buf[256];
   if (prm.mode == 1)
-    std::snprintf(buf, sizeof buf, "{\"mode\": \"kernels\", \"systems\": %d, \"pairs\": %lld, \"ms\": %.4f}",
-                  B.nsys, B.pairs, prm.ms);
+    std::snprintf(buf, sizeof buf,
+                  "{\"mode\": \"kernels\", \"branches\": %d, \"systems\": %d, \"pairs\": %lld, \"ms\": %.4f, "
+                  "\"source\": \"%s\"}",
+                  std::max(1, std::min(prm.branches, B.nsys)), B.nsys, B.pairs, prm.ms, B.prm_source);
   else
     std::snprintf(buf, sizeof buf,
                   "{\"mode\": \"persistent\", \"tile\": %d, \"slots\": %d, \"units_per_ticket\": %d, "
                   "\"blocks_per_cu\": %d, \"grid\": %d, \"segments\": %d, \"units\": %lld, \"pairs\": %lld, "
-                  "\"ms\": %.4f}",
-                  prm.tile, prm.slots, prm.units_per_ticket, bpc, grid, B.nseg, total, B.pairs, prm.ms);
+                  "\"ms\": %.4f, \"source\": \"%s\"}",
+                  prm.tile, prm.slots, prm.units_per_ticket, bpc, grid, B.nseg, total, B.pairs, prm.ms, B.prm_source);
   B.info = buf;
   return FOCK_OK;
 }
@@ -1736,7 +1800,14 @@ fock_status batch_tune_and_capture(BatchPlanImpl& B, const std::string& cache) {
       const int v = std::atoi(tk);
       if (v >= 1 && v <= (1 << 20)) best.units_per_ticket = v;
     }
-  } else if (force_mode >= 0 || !tune_cache_lookup(cache, key, &best)) {
+    if (const char* nb = std::getenv("FOCK_BATCH_BRANCHES")) {
+      const int v = std::atoi(nb);
+      if (v >= 1 && v <= kBatchMaxBranches) best.branches = v;
+    }
+  } else if (force_mode < 0 && tune_cache_lookup(cache, key, &best)) {
+    B.prm_source = "tune cache";
+  } else {
+    B.prm_source = "tuned";
     std::map<std::tuple<int, int, int>, double> seen;
     auto eval = [&](int tile, int upt, int bpc, double* ms) -> fock_status {
       auto k = std::make_tuple(tile, upt, bpc);
@@ -1792,17 +1863,21 @@ fock_status batch_tune_and_capture(BatchPlanImpl& B, const std::string& cache) {
       best.mode = 0;
     }
     if (force_mode != 0) {
-      // the per-shape kernels of every system in one graph
-      BatchParams p;
-      p.mode = 1;
-      double ms = 0.0;
-      if ((st = batch_capture<T>(B, p)) != FOCK_OK) return st;
-      if ((st = batch_time<T>(B, &ms)) != FOCK_OK) return st;
-      if (const char* lg = std::getenv("FOCK_TUNE_LOG"); lg && std::atoi(lg) != 0)
-        std::fprintf(stderr, "[fock tune] per-shape kernels: %.3f ms\n", ms);
-      if (best_ms < 0.0 || ms < best_ms) {
-        best = p;
-        best.ms = ms;
+      // the per-shape kernels of every system in one graph, on 1 .. 4 branches
+      for (int nbr = 1; nbr <= std::min(kBatchMaxBranches, B.nsys); ++nbr) {
+        BatchParams p;
+        p.mode = 1;
+        p.branches = nbr;
+        double ms = 0.0;
+        if ((st = batch_capture<T>(B, p)) != FOCK_OK) return st;
+        if ((st = batch_time<T>(B, &ms)) != FOCK_OK) return st;
+        if (const char* lg = std::getenv("FOCK_TUNE_LOG"); lg && std::atoi(lg) != 0)
+          std::fprintf(stderr, "[fock tune] per-shape kernels on %d branch(es): %.3f ms\n", nbr, ms);
+        if (best_ms < 0.0 || ms < best_ms) {
+          best = p;
+          best.ms = ms;
+          best_ms = ms;
+        }
       }
     }
     if (force_mode < 0) tune_cache_store(cache, key, best);

@@ -22,9 +22,14 @@ struct BatchParams {
   int blocks_per_cu = 1;     // persistent blocks per CU (selects the register budget)
   double ms = 0.0;           // measured replay time when tuned
   // 0: one persistent kernel runs every stage of every system; 1: the graph
-  // holds each system's own schedule of per-shape kernels, one after another
+  // holds each system's own schedule of per-shape kernels
   int mode = 0;
+  // mode 1: independent graph branches the systems are split over (1: one
+  // after another)
+  int branches = 1;
 };
+
+constexpr int kBatchMaxBranches = 4;
 
 // Ranges the persistent schedule is built for.  slots below kBatchStages
 // would make a pair tile wait on a later tile of the same buffer ring (a
@@ -34,7 +39,8 @@ struct BatchParams {
 inline bool batch_params_valid(const BatchParams& p) {
   return (p.tile == 8 || p.tile == 16) && p.slots >= kBatchStages && p.slots <= kBatchSlots &&
          p.units_per_ticket >= 1 && p.units_per_ticket <= (1 << 20) && p.blocks_per_cu >= 1 &&
-         p.blocks_per_cu <= 8 && (p.mode == 0 || p.mode == 1) && std::isfinite(p.ms) && p.ms >= 0.0;
+         p.blocks_per_cu <= 8 && (p.mode == 0 || p.mode == 1) && p.branches >= 1 &&
+         p.branches <= kBatchMaxBranches && std::isfinite(p.ms) && p.ms >= 0.0;
 }
 
 // Entry for `key` in the cache file at `path` (the last one if repeated).
@@ -50,11 +56,12 @@ inline bool tune_cache_lookup(const std::string& path, const std::string& key, B
     const char* at = std::strstr(line, pat.c_str());
     if (!at) continue;
     BatchParams p;
-    // entries written before the mode field existed describe the persistent kernel
+    // entries written before the mode field existed describe the persistent
+    // kernel, those before the branches field one branch
     const int got = std::sscanf(at + pat.size(),
                                 " \"tile\": %d, \"slots\": %d, \"units_per_ticket\": %d, \"blocks_per_cu\": %d, "
-                                "\"ms\": %lf, \"mode\": %d",
-                                &p.tile, &p.slots, &p.units_per_ticket, &p.blocks_per_cu, &p.ms, &p.mode);
+                                "\"ms\": %lf, \"mode\": %d, \"branches\": %d",
+                                &p.tile, &p.slots, &p.units_per_ticket, &p.blocks_per_cu, &p.ms, &p.mode, &p.branches);
     if (got >= 5 && batch_params_valid(p)) {
       *out = p;
       found = true;
@@ -85,8 +92,8 @@ inline void tune_cache_store(const std::string& path, const std::string& key, co
   char buf[512];
   std::snprintf(buf, sizeof buf,
                 "\"%s\": {\"tile\": %d, \"slots\": %d, \"units_per_ticket\": %d, \"blocks_per_cu\": %d, \"ms\": %.4f, "
-                "\"mode\": %d}",
-                key.c_str(), p.tile, p.slots, p.units_per_ticket, p.blocks_per_cu, p.ms, p.mode);
+                "\"mode\": %d, \"branches\": %d}",
+                key.c_str(), p.tile, p.slots, p.units_per_ticket, p.blocks_per_cu, p.ms, p.mode, p.branches);
   keep.push_back(buf);
   const std::string tmp = path + ".tmp";
   FILE* f = std::fopen(tmp.c_str(), "w");

@@ -161,6 +161,9 @@ int main(int argc, char** argv) {
                    "\"mode7\": {\"tile\": 16, \"slots\": 6, \"units_per_ticket\": 32, \"blocks_per_cu\": 1, \"ms\": 1, \"mode\": 7},\n"
                    "\"bpc0\": {\"tile\": 16, \"slots\": 6, \"units_per_ticket\": 32, \"blocks_per_cu\": 0, \"ms\": 1, \"mode\": 0},\n"
                    "\"nanms\": {\"tile\": 16, \"slots\": 6, \"units_per_ticket\": 32, \"blocks_per_cu\": 1, \"ms\": nan, \"mode\": 0},\n"
+                   "\"branches9\": {\"tile\": 16, \"slots\": 6, \"units_per_ticket\": 32, \"blocks_per_cu\": 1, \"ms\": 1, \"mode\": 1, \"branches\": 9},\n"
+                   "\"branches0\": {\"tile\": 16, \"slots\": 6, \"units_per_ticket\": 32, \"blocks_per_cu\": 1, \"ms\": 1, \"mode\": 1, \"branches\": 0},\n"
+                   "\"branches3\": {\"tile\": 16, \"slots\": 6, \"units_per_ticket\": 32, \"blocks_per_cu\": 1, \"ms\": 1, \"mode\": 1, \"branches\": 3},\n"
                    "\"short\": {\"tile\": 16, \"slots\": 6},\n"
                    "\"junk\": {garbage},\n"
                    "\"twice\": {\"tile\": 8, \"slots\": 6, \"units_per_ticket\": 32, \"blocks_per_cu\": 1, \"ms\": 1, \"mode\": 0},\n"
@@ -172,7 +175,10 @@ int main(int argc, char** argv) {
     EXPECT(fockx::tune_cache_lookup(path, "ok", &p) && p.tile == 8 && p.units_per_ticket == 32 &&
            p.blocks_per_cu == 2 && p.mode == 0);
     EXPECT(fockx::tune_cache_lookup(path, "old", &p) && p.slots == 4 && p.mode == 0);
+    EXPECT(fockx::tune_cache_lookup(path, "branches3", &p) && p.mode == 1 && p.branches == 3);
+    EXPECT(fockx::tune_cache_lookup(path, "ok", &p) && p.branches == 1);
     for (const char* bad : {"slots9", "slots0", "slots3", "tile32", "ticket0", "ticketneg", "mode7", "bpc0", "nanms",
+                            "branches9", "branches0",
                             "short", "junk", "twice", "absent"}) {
       fockx::BatchParams q;
       const bool got = fockx::tune_cache_lookup(path, bad, &q);
@@ -186,9 +192,10 @@ int main(int argc, char** argv) {
     w.tile = 16;
     w.units_per_ticket = 512;
     w.mode = 1;
+    w.branches = 2;
     w.ms = 12.5;
     fockx::tune_cache_store(path, "new", w);
-    EXPECT(fockx::tune_cache_lookup(path, "new", &p) && p.units_per_ticket == 512 && p.mode == 1);
+    EXPECT(fockx::tune_cache_lookup(path, "new", &p) && p.units_per_ticket == 512 && p.mode == 1 && p.branches == 2);
     EXPECT(fockx::tune_cache_lookup(path, "ok", &p) && p.tile == 8);
     w.slots = 40;
     fockx::tune_cache_store(path, "bad_store", w);

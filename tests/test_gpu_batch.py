@@ -29,10 +29,15 @@ def _small_batch():
 
 
 @pytest.mark.parametrize("prec", ["c128", "c64"])
-@pytest.mark.parametrize("mode", ["0", "1", "auto"])
+@pytest.mark.parametrize("mode", ["0", "1", "1-branches3", "auto"])
 def test_batch_small_vs_single_and_oracle(prec, mode, tmp_path, monkeypatch):
     import torch
     F = _F()
+    if mode == "1-branches3":
+        # the per-shape schedule on three independent graph branches, untuned
+        monkeypatch.setenv("FOCK_BATCH_TUNE", "0")
+        monkeypatch.setenv("FOCK_BATCH_BRANCHES", "3")
+        mode = "1"
     if mode != "auto":
         monkeypatch.setenv("FOCK_BATCH_MODE", mode)
     cdt = torch.complex128 if prec == "c128" else torch.complex64
@@ -48,6 +53,8 @@ def test_batch_small_vs_single_and_oracle(prec, mode, tmp_path, monkeypatch):
     report(f"batch small {prec} schedule", **{k: v for k, v in plan.info().items()})
     if mode != "auto":
         assert plan.info()["mode"] == ("persistent" if mode == "0" else "kernels")
+    if plan.info()["mode"] == "kernels":
+        assert 1 <= plan.info()["branches"] <= 3
     plan.apply()
     plan.check()
     outs = [host(o).copy() for o in plan.outs]
