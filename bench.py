@@ -366,15 +366,11 @@ def traced(fock, step, steps):
     return tr
 
 
-# What bounds each kernel class, from the rocprofv3 counters of the
-# workloads: in FP32 (no packed instructions) the plane and pencil transforms
-# spend more vector-ALU time than HBM time per point; in FP64 the transforms
-# and everywhere the streaming multiply-accumulate are bound by HBM.
-ALU_BOUND_FP32 = ("p1_pair_plane_fwd", "p2_pencil_kernel", "p2_pencil_energy", "p3_plane_inv_mac")
-
-
-def class_bound(kernel, fp64):
-    return "alu" if not fp64 and kernel in ALU_BOUND_FP32 else "hbm"
+# A kernel class is set against the vector-ALU roofline when its algorithmic
+# intensity (flops per byte moved) lies above the ridge point of the two
+# peaks, else against HBM.  In FP32 only the pair pass (P1), which reads its
+# two operands from cache and writes one pair buffer, lies above the ridge.
+RIDGE_FLOP_PER_BYTE = VALU_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9)
 
 
 def roofline(tr, acc, steps, workload, fp64=True, flops=None):
@@ -397,7 +393,8 @@ def roofline(tr, acc, steps, workload, fp64=True, flops=None):
         tfs = fl_launch / (avg_ms * 1e-3) / 1e12
         rec.update({"flops_per_launch": round(fl_launch), "valu_tflops": round(tfs, 2),
                     "valu_frac": round(tfs / VALU_PEAK_TFLOPS, 4)})
-        if class_bound(dom, fp64) == "alu":
+        rec["flop_per_byte"] = round(fl_launch / per_launch, 2)
+        if fl_launch / per_launch > RIDGE_FLOP_PER_BYTE:
             rec.update({"bound": "alu", "achieved": round(tfs, 2), "peak": round(VALU_PEAK_TFLOPS, 1),
                         "unit": "TFLOP/s", "frac": round(tfs / VALU_PEAK_TFLOPS, 4)})
     return rec
