@@ -681,7 +681,7 @@ def cpu_workers(ntasks):
     return max(1, min(len(os.sched_getaffinity(0)), 16, ntasks))
 
 
-def cpu_baseline_batch(systems, nocc=16):
+def cpu_baseline_batch(systems, nocc=48):
     """The oracle on every system of the batch: target 0 against the first
     `nocc` occupied orbitals, one task per system, on the host cores.  The
     per-pair time of each system, weighted by its n_occ x n_tgt pairs, gives
