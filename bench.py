@@ -373,11 +373,39 @@ def traced(fock, step, steps):
 RIDGE_FLOP_PER_BYTE = VALU_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9)
 
 
+_COPY_GBS = None
+
+
+def copy_gbs():
+    """HBM rate of a plain device-to-device copy on this GPU (1 GiB, bytes
+    read + written over the time of one copy, best of five), measured once:
+    the practical ceiling the streaming passes are compared with."""
+    global _COPY_GBS
+    if _COPY_GBS is None:
+        import torch
+        src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        best = None
+        for _ in range(5):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            dst.copy_(src)
+            b.record()
+            b.synchronize()
+            ms = a.elapsed_time(b)
+            best = ms if best is None else min(best, ms)
+        del src, dst
+        torch.cuda.empty_cache()
+        _COPY_GBS = 2.0 * (1 << 30) / (best * 1e-3) / 1e9
+    return _COPY_GBS
+
+
 def roofline(tr, acc, steps, workload, fp64=True, flops=None):
     """The dominant kernel class (most time) against its roofline: HBM bytes
     per launch over the launch time, or for an ALU-bound class algorithmic
     flops over the launch time against the vector-ALU peak.  Both rates are
-    reported."""
+    reported, and the HBM rate also against a plain device copy."""
     pair_cls = [k for k in acc if k in tr and tr[k][1]]
     dom = max(pair_cls, key=lambda k: tr[k][0])
     ms, launches = tr[dom]
@@ -388,6 +416,12 @@ def roofline(tr, acc, steps, workload, fp64=True, flops=None):
            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": pmc_traffic(workload, dom), "kernel": dom,
            "avg_launch_ms": round(avg_ms, 5), "bytes_per_launch": round(per_launch),
            "hbm_gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+    cg = copy_gbs()
+    rec.update({"copy_gbs": round(cg, 1), "hbm_vs_copy": round(gbs / cg, 4)})
+    # every pair-pass class: algorithmic HBM rate over its summed launch time
+    rec["classes"] = {k: {"ms": round(tr[k][0], 3), "gbs": round(acc[k][0] * steps / (tr[k][0] * 1e-3) / 1e9, 1),
+                          "vs_copy": round(acc[k][0] * steps / (tr[k][0] * 1e-3) / 1e9 / cg, 3)}
+                      for k in pair_cls}
     if flops and dom in flops:
         fl_launch = flops[dom] * steps / launches
         tfs = fl_launch / (avg_ms * 1e-3) / 1e12
@@ -505,6 +539,17 @@ def tile_bytes(lf):
             "p3_plane_inv_mac": 256 * lf + 256, "p3_second": 256 + 16 + 16 + 32 + 32}
 
 
+def tile_flops(n):
+    """Algorithmic flops per launch and grid point of each class on full 16 x
+    16 tiles, for the k-mesh workload (pair_flops per pair times 256 pairs;
+    the streaming MAC accumulates both halves)."""
+    pf = pair_flops(n)
+    l1 = float(np.log2(n[0]))
+    return {"p1_pair_plane_fwd": 256 * pf["p1_pair_plane_fwd"], "p2_pencil_kernel": 256 * pf["p2_pencil_kernel"],
+            "p2_pencil_energy": 256 * (5 * l1 + 4), "p3_plane_inv_mac": 256 * pf["p3_inplace"],
+            "p3_second": 256 * 2 * pf["mac_half"]}
+
+
 def kmesh_grad(name, args, cpu):
     import torch
     from paper_1305_7313_amd import fock
@@ -545,7 +590,9 @@ def kmesh_grad(name, args, cpu):
         tr = traced(fock, step, 1)
         tb = tile_bytes(live_fraction(s.miller, n))
         acc = {k: [tb[k] * N * 8 * tr[k][1], tr[k][1]] for k in tb if k in tr and tr[k][1]}
-        rec["roofline"] = roofline(tr, acc, 1, name)
+        tf = tile_flops(n)
+        fl = {k: tf[k] * N * tr[k][1] for k in tf if k in tr and tr[k][1]}
+        rec["roofline"] = roofline(tr, acc, 1, name, fp64=False, flops=fl)
         rec["kernels"] = {k: {"ms_per_step": round(v[0], 4), "launches_per_step": v[1]} for k, v in tr.items() if v[1]}
     return rec
 
