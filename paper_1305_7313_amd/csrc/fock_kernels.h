@@ -479,7 +479,10 @@ constexpr PlaneTune plane_tune(int tbytes, int n2, int n3, int mode) {
       if (mirror) return PlaneTune{512, false, 2};
       return mac ? PlaneTune{256, false, 2} : PlaneTune{256, true, 1};
     }
-    if (n2 == 96 && n3 == 128) return p1 ? PlaneTune{768, true, 2} : inv ? PlaneTune{512, true, 2} : PlaneTune{1024, true, 1};
+    // P1 at 512 threads: the only width at which its 24 values per thread fit
+    // without spilling (at 768 the register cap of a 12-wave workgroup spills
+    // 58 registers, and the scratch traffic doubles its HBM bytes)
+    if (n2 == 96 && n3 == 128) return p1 ? PlaneTune{512, true, 1} : inv ? PlaneTune{512, true, 2} : PlaneTune{1024, true, 1};
     if (n2 == 96 && n3 == 96) return PlaneTune{768, true, 1};
     if (n2 == 72 && n3 == 72) return pair ? PlaneTune{720, true, 1} : PlaneTune{576, true, 1};
     if (n2 == 48 && n3 == 64) return PlaneTune{256, false, 1};
