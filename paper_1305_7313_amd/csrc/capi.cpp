@@ -594,6 +594,23 @@ struct Engine {
     return sizeof(T) == 8 && P.n[2] <= 64 ? 2 : 1;
   }
 
+  // Apply of an occupied block to a different target block (or at q != 0):
+  //   0  fused inverse plane FFT + multiply-accumulate, one workgroup per
+  //      (target, plane) looping over the occupied orbitals of the tile;
+  //   1  in-place inverse plane FFT of every pair of the tile, then the
+  //      streaming multiply-accumulate (forward half only).
+  // The fused pass holds a plane of accumulators beside the plane being
+  // transformed; in FP64 beyond 96 x 96 that spills heavily, and schedule 1
+  // is faster there (96 x 96 x 128, 64 x 64 orbitals: 112 against 150 ms).
+  // Elsewhere the fused pass wins by 5-37% (FP32 at every size, FP64 up to
+  // 96 x 96), since it moves the pair buffer once instead of three times.
+  int apply_schedule() const {
+    const char* e = std::getenv("FOCK_APPLY_SCHEDULE");
+    const int env = e ? std::atoi(e) : -1;
+    if (env == 0 || env == 1) return env;
+    return sizeof(T) == 8 && P.n[1] * P.n[2] > 96 * 96 ? 1 : 0;
+  }
+
   // Live plane columns of the pair buffer (FOCK_PRUNE=0: every column).
   const signed char* live() const {
     const char* e = std::getenv("FOCK_PRUNE");
@@ -722,6 +739,31 @@ struct Engine {
           if (J.energy) {
             FX_TRACE(KC_REDUCE);
             FX_HIP(launch_energy_tile(epart, ngroups, J.fA, J.gB, i0, j0, ti, tj, 0, 0, J.escale, tile_e + tile, s));
+          } else if (apply_schedule() == 1) {
+            {
+              FX_TRACE(KC_P3);
+              PlaneArgs lv = plane_args(nullptr, nullptr, nullptr, nullptr, nullptr, 0, 0, 0, 0);
+              lv.x = w;
+              lv.live = live();
+              lv.nb = ti * tj;
+              FX_HIP(launch_plane<T>(PLANE_INV, P.n[1], P.n[2], lv, ti * tj * P.n[0], s));
+            }
+            // acc holds the tile's targets from row 0: target jj at row jj
+            MacArgs ma{};
+            ma.w = w;
+            ma.phi = J.phiA;
+            ma.f = J.fA;
+            ma.acc = acc;  // mirror half: not used
+            ma.phi_b = J.phiB;
+            ma.acc_b = acc;
+            ma.N = P.N;
+            ma.i0 = i0;
+            ma.j0 = 0;
+            ma.ti = ti;
+            ma.tj = tj;
+            ma.mirror = 0;
+            FX_TRACE(KC_P3B);
+            FX_HIP(launch_mac_pair<T>(ma, s));
           } else {
             FX_TRACE(KC_P3);
             FX_HIP(launch_plane<T>(PLANE_INV_MAC, P.n[1], P.n[2], la, tj * P.n[0], s));

@@ -690,9 +690,9 @@ struct MacArgs {
   const void* phi;     // occupied orbitals (set A) in real space [n][N]
   const double* f;     // occupations of set A
   void* acc;           // accumulators of set A [n][N] (mirror half)
-  const void* phi_b;   // target orbitals (set B) and their weights / accumulators
-  const double* f_b;   //   (forward half); all three equal the set-A ones when
-  void* acc_b;         //   one block is applied to itself
+  const void* phi_b;   // target orbitals (set B) and their weights (mirror
+  const double* f_b;   //   half only) and accumulators (forward half); all
+  void* acc_b;         //   three equal the set-A ones when one block is applied to itself
   long long N;
   int i0, j0, ti, tj, mirror;
   int tri;             // diagonal tile: pairs ii <= jj at tri_slot(ii, jj); forward ii <= jj, mirror ii < jj
@@ -724,7 +724,8 @@ __global__ __launch_bounds__(256) void mac_pair_kernel(MacArgs A) {
   for (int jj = 0; jj < tj; ++jj) {
     const long long oj = (long long)(A.j0 + jj) * N;
     const cx<T> aj0 = acc_b[oj];
-    const cx<T> fphi_j = cscale<T>(phi_b[oj], T(f_b[A.j0 + jj]));
+    // the forward half alone (mirror == 0) reads neither phi_b nor f_b
+    const cx<T> fphi_j = mirror ? cscale<T>(phi_b[oj], T(f_b[A.j0 + jj])) : mk<T>(T(0), T(0));
     const int iend = tri ? jj + 1 : ti;  // forward: ii < iend; mirror: ii < jj on a diagonal tile
     cx<T> v[kMacTile];
 #pragma unroll

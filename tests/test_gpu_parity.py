@@ -116,9 +116,14 @@ def test_cases_apply_energy_grad(case, prec, schedule, monkeypatch):
     import torch
     F = _F()
     name, c, s, occ, tgt, f, g, q, v_ref, e_ref, go_ref, gt_ref = case
-    if schedule != "0" and not c.get("self"):
-        pytest.skip("the schedule choice only exists for one block at q = 0")
-    monkeypatch.setenv("FOCK_SYM_SCHEDULE", schedule)
+    # one block at q = 0 takes the pair-symmetric schedules 0-2, any other
+    # apply the fused (0) or streaming (1) schedule
+    if c.get("self"):
+        monkeypatch.setenv("FOCK_SYM_SCHEDULE", schedule)
+    elif schedule == "2":
+        pytest.skip("the apply of two blocks has schedules 0 and 1")
+    else:
+        monkeypatch.setenv("FOCK_APPLY_SCHEDULE", schedule)
     print(f"[case] {name} {prec} schedule={schedule}", flush=True)
     cell = F.Cell(s.a, s.n, s.miller, g0=c["g0"], gb_alpha=0.7, nq=(2, 2, 2))
     co = dev(occ, _ctype(prec))
@@ -216,6 +221,12 @@ def test_every_path_is_bitwise_reproducible(prec, monkeypatch):
         a = host(F.fock_apply(cell, (0, 0, 0), c, f, c))
         b = host(F.fock_apply(cell, (0, 0, 0), c, f, c))
         assert np.array_equal(a, b), sched
+    t = c[:19].contiguous()
+    for sched in ("0", "1"):
+        monkeypatch.setenv("FOCK_APPLY_SCHEDULE", sched)
+        a = host(F.fock_apply(cell, (0.1, 0.0, -0.05), c, f, t))
+        b = host(F.fock_apply(cell, (0.1, 0.0, -0.05), c, f, t))
+        assert np.array_equal(a, b), "apply " + sched
     a = host(F.fock_apply_gamma(cell, g, f[:21].contiguous()))
     b = host(F.fock_apply_gamma(cell, g, f[:21].contiguous()))
     assert np.array_equal(a, b)
