@@ -496,8 +496,13 @@ constexpr PlaneTune plane_tune(int tbytes, int n2, int n3, int mode) {
   }
   if (n2 == 96 && n3 == 96) return mac ? PlaneTune{384, false, 1} : inv ? PlaneTune{768, true, 1} : PlaneTune{768, false, 1};
   if (n2 == 72 && n3 == 72) {
-    if (p1 || fwdmac || mirror) return PlaneTune{720, false, 1};
-    return inv ? PlaneTune{720, true, 2} : PlaneTune{576, false, 1};
+    // P1 and the in-place inverse at 504 threads (8 waves), re-timed on the
+    // padded exchange layouts: three planes per CU in flight where two
+    // workgroups of 720 threads (12 waves) fit (16-system batch 1086 -> 1071
+    // ms, 72^3 k-mesh 8723 -> 8246 ms)
+    if (p1) return PlaneTune{504, false, 1};
+    if (fwdmac || mirror) return PlaneTune{720, false, 1};
+    return inv ? PlaneTune{504, true, 1} : PlaneTune{576, false, 1};
   }
   if (n2 == 64 && n3 == 64) return p1 ? PlaneTune{256, true, 1} : PlaneTune{512, false, 1};
   if (n2 == 48 && n3 == 64) return PlaneTune{256, false, 1};
@@ -536,10 +541,13 @@ struct PencilTune {
 };
 constexpr PencilTune pencil_tune(int tbytes, int n1, int mode = -1) {
   if (n1 == 24) return PencilTune{64, 128, -1, 1};
-  if (n1 == 48) return PencilTune{64, 128, -1, 1};
+  // FP32 P2 on 48- and 64-point pencils: 512 threads (re-timed on a full
+  // 16 x 16 tile: 48: 88 -> 81 us, 64: 191 -> 180 us)
+  if (n1 == 48) return tbytes == 4 && mode == PENCIL_FKI ? PencilTune{64, 512, -1, 1} : PencilTune{64, 128, -1, 1};
   if (n1 == 64) {
     // FP64 P2: 512 threads on an unsplit 66.5 KB tile, two per CU (-3.5%)
     if (tbytes == 8 && mode == PENCIL_FKI) return PencilTune{64, 512, 0, 2};
+    if (mode == PENCIL_FKI) return PencilTune{64, 512, -1, 1};
     return PencilTune{64, 256, -1, 1};
   }
   if (n1 == 72) return tbytes == 4 ? PencilTune{32, 128, -1, 1} : PencilTune{32, 256, -1, 1};

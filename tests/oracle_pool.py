@@ -13,6 +13,7 @@ import os
 import numpy as np
 
 _CACHE = {}
+C3Q_SHIFT = (0.05, -0.03, 0.02)  # bohr^-1
 
 
 def _workload(name):
@@ -24,6 +25,10 @@ def _workload(name):
         elif name == "c3":
             s, c = synth.config3()
             _CACHE[name] = (s, {0: c}, {0: np.zeros(3)})
+        elif name == "c3q":
+            # config 3's orbitals as two sets: targets at k = C3Q_SHIFT, occupied at k = 0
+            s, c = synth.config3()
+            _CACHE[name] = (s, {0: c, 1: c}, {0: np.array(C3Q_SHIFT), 1: np.zeros(3)})
         elif name == "c5":
             s, kpts, orbs = synth.config5()
             _CACHE[name] = (s, dict(enumerate(orbs)), dict(enumerate(kpts)))
