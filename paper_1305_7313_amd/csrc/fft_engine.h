@@ -221,24 +221,29 @@ template <int R, int DIR, typename T> __device__ __forceinline__ void dft(cx<T>*
 //   L      transform length, R radix, P span (product of earlier radices)
 //   BATCH  number of transforms in the tile
 //   ROW    true: transform along the contiguous axis: element (b, x) is at
-//          tile row b, column x; lanes walk the butterfly index i first
-//          false: along the strided axis: element (b, x) is at row x,
-//          column b; lanes walk the column b first
+//          tile row b, column x; false: along the strided axis: element
+//          (b, x) is at row x, column b
+//   LB     lanes walk the batch index b first (default for a column pass,
+//          whose lanes then walk the tile's columns); otherwise the
+//          butterfly index i (default for a row pass, whose lanes then walk
+//          the row).  Either keeps HBM accesses coalesced in the default; a
+//          row pass that only touches LDS may walk the batch (rows) instead,
+//          which spreads an exchange's lanes over rows, hence banks.
 //   SL     row stride of the tile in LDS (padded; in elements)
 // Thread t owns butterflies beta = t + s W, s < NS.  W is a multiple of the
-// lane-fastest extent (NI for ROW, BATCH for COL), so (b, i) are affine in s
-// and every element position is base(t) + constant: the per-element offsets
+// lane-fastest extent (BATCH if LB, else NI), so (b, i) are affine in s and
+// every element position is base(t) + constant: the per-element offsets
 // fold into instruction immediates.
 // ---------------------------------------------------------------------------
-template <int L_, int R_, int P_, int BATCH_, bool ROW_, int W_> struct Pass {
+template <int L_, int R_, int P_, int BATCH_, bool ROW_, int W_, bool LB_ = !ROW_> struct Pass {
   static constexpr int L = L_, R = R_, P = P_, BATCH = BATCH_, W = W_;
-  static constexpr bool ROW = ROW_;
+  static constexpr bool ROW = ROW_, LB = LB_;
   static constexpr int NI = L / R;           // butterflies per transform
   static constexpr int NBF = BATCH * NI;     // butterflies in the tile
   static constexpr int NS = (NBF + W - 1) / W;
   static constexpr bool EXACT = (NBF % W) == 0;
   static constexpr int NV = NS * R;          // register values per thread
-  static constexpr int FAST = ROW ? NI : BATCH;
+  static constexpr int FAST = LB ? BATCH : NI;
   static_assert(L % R == 0 && L % (P * R) == 0, "bad pass");
   static_assert(P == 1 || P == NI, "two-pass factorisations only");
   static_assert(W % FAST == 0, "block size must be a multiple of the lane-fastest extent");
@@ -250,18 +255,18 @@ template <int L_, int R_, int P_, int BATCH_, bool ROW_, int W_> struct Pass {
   };
   __device__ static __forceinline__ Lane lane(int t) {
     Lane l;
-    if constexpr (ROW) {
-      l.i0 = t % NI;
-      l.b0 = t / NI;
-    } else {
+    if constexpr (LB) {
       l.b0 = t % BATCH;
       l.i0 = t / BATCH;
+    } else {
+      l.i0 = t % NI;
+      l.b0 = t / NI;
     }
     l.tlim = NBF - (NS - 1) * W;
     return l;
   }
-  __device__ static __forceinline__ int b_of(const Lane& l, int s) { return ROW ? l.b0 + s * STEP : l.b0; }
-  __device__ static __forceinline__ int i_of(const Lane& l, int s) { return ROW ? l.i0 : l.i0 + s * STEP; }
+  __device__ static __forceinline__ int b_of(const Lane& l, int s) { return LB ? l.b0 : l.b0 + s * STEP; }
+  __device__ static __forceinline__ int i_of(const Lane& l, int s) { return LB ? l.i0 + s * STEP : l.i0; }
   __device__ static __forceinline__ bool active(const Lane& l, int t, int s) {
     return EXACT || s < NS - 1 || t < l.tlim;
   }
@@ -282,10 +287,16 @@ template <> struct Factor<72> { static constexpr int R0 = 8, R1 = 9; };
 template <> struct Factor<96> { static constexpr int R0 = 8, R1 = 12; };
 template <> struct Factor<128> { static constexpr int R0 = 8, R1 = 16; };
 
-// The two passes of a length-L transform over a tile.
-template <int L, int BATCH, bool ROW, int W> struct Axis {
-  using P0 = Pass<L, Factor<L>::R0, 1, BATCH, ROW, W>;
-  using P1 = Pass<L, Factor<L>::R1, Factor<L>::R0, BATCH, ROW, W>;
+// The two passes of a length-L transform over a tile (radices FR0 then FR1),
+// with the default lane order (P0, P1) and, for a row transform, with the
+// lanes walking the rows (P0b, P1b: for a pass that reads and writes only LDS).
+template <int L, int BATCH, bool ROW, int W, int FR0 = Factor<L>::R0, int FR1 = Factor<L>::R1> struct Axis {
+  static_assert(FR0 * FR1 == L, "bad factorisation");
+  using P0 = Pass<L, FR0, 1, BATCH, ROW, W>;
+  using P1 = Pass<L, FR1, FR0, BATCH, ROW, W>;
+  static constexpr bool LB_OK = W % BATCH == 0;  // the batch can be the lane-fastest index
+  using P0b = Pass<L, FR0, 1, BATCH, ROW, W, LB_OK>;
+  using P1b = Pass<L, FR1, FR0, BATCH, ROW, W, LB_OK>;
   static constexpr int NV = P0::NV > P1::NV ? P0::NV : P1::NV;
 };
 

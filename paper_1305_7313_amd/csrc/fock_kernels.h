@@ -16,6 +16,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
 #include <utility>
 
 #include "fft_engine.h"
@@ -179,7 +180,12 @@ template <typename T, int N2, int N3, int W, bool SPLIT> struct PlaneGeom {
   static constexpr int PLANE = N2 * N3;
   static constexpr int XBYTES =
       plane_slots<N3, plane_tile_pad<T, N3>()>(N2) * (SPLIT ? (int)sizeof(T) : 2 * (int)sizeof(T));
-  using Rw = Axis<N3, N2, true, W>;   // transforms along i3, one per row
+  // transforms along i3, one per row.  On the compact (unpadded) tile the
+  // rows take the larger radix first: the first row pass then writes column
+  // R1 i + r from lane i (for 96: 12 i + r), which with the lanes of a row
+  // pass and the odd row stride lands every lane of a wave in its own bank.
+  using Rw = std::conditional_t<plane_tile_pad<T, N3>(), Axis<N3, N2, true, W>,
+                                Axis<N3, N2, true, W, Factor<N3>::R1, Factor<N3>::R0>>;
   using Cl = Axis<N2, N3, false, W>;  // transforms along i2, one per column
   static constexpr int NV = Rw::NV > Cl::NV ? Rw::NV : Cl::NV;
 };
@@ -188,12 +194,20 @@ template <typename T, int N2, int N3, int W, bool SPLIT, int MODE>
 __device__ __forceinline__ void plane_body(const PlaneArgs& A, int lid, unsigned char* smem, const cx<T>* tw2,
                                            const cx<T>* tw3) {
   using Cfg = PlaneGeom<T, N2, N3, W, SPLIT>;
-  using R0 = typename Cfg::Rw::P0;
-  using R1 = typename Cfg::Rw::P1;
+  constexpr bool PAD = plane_tile_pad<T, N3>();
+  // On the compact (unpadded) tile, the row pass that touches only LDS walks
+  // the rows with its lanes: the forward direction's second row pass, the
+  // backward direction's first.  Its exchanges then spread the lanes of a
+  // wave over rows (stride COLS + 1) instead of a row's 8-element-strided
+  // columns, and stall on far fewer bank conflicts.  The V-multiply mode,
+  // whose row passes also meet V(r) in HBM, keeps the default order.
+  constexpr bool fwd_dir = MODE == PLANE_PAIR_FWD || MODE == PLANE_PAIR_FWD_G || MODE == PLANE_FWD;
+  constexpr bool rows_lb = !PAD && MODE != PLANE_VMUL;
+  using R0 = std::conditional_t<rows_lb && !fwd_dir, typename Cfg::Rw::P0b, typename Cfg::Rw::P0>;
+  using R1 = std::conditional_t<rows_lb && fwd_dir, typename Cfg::Rw::P1b, typename Cfg::Rw::P1>;
   using C0 = typename Cfg::Cl::P0;
   using C1 = typename Cfg::Cl::P1;
   constexpr int PLANE = Cfg::PLANE;
-  constexpr bool PAD = plane_tile_pad<T, N3>();
   const int t = threadIdx.x;
   const long long N = A.N;
   cx<T> v[Cfg::NV];
@@ -461,7 +475,7 @@ __device__ __forceinline__ void plane_body(const PlaneArgs& A, int lid, unsigned
 struct PlaneTune {
   int w;
   bool split;
-  int minb;
+  int minb;  // the launch bound's minimum waves per SIMD
 };
 constexpr PlaneTune plane_tune(int tbytes, int n2, int n3, int mode) {
   const bool p1 = mode == PLANE_PAIR_FWD || mode == PLANE_PAIR_FWD_G, inv = mode == PLANE_INV,
@@ -535,7 +549,8 @@ __global__ __launch_bounds__(W, MINB) void plane_kernel(PlaneArgs A) {
 // cb pencils per workgroup (the host sizes grids and energy partials with
 // it, so it depends on the length and precision only), w threads; split: 1/0
 // forces the two-round FP64 exchange on or off, -1 takes it when the tile
-// exceeds 64 KB; minb: workgroups per CU the registers are budgeted for.
+// exceeds 64 KB; minb: the launch bound's minimum waves per SIMD (registers
+// per thread are capped at 512 / minb).
 struct PencilTune {
   int cb, w, split, minb;
 };
