@@ -181,9 +181,9 @@ template <typename T, int N2, int N3, int W, bool SPLIT> struct PlaneGeom {
   static constexpr int XBYTES =
       plane_slots<N3, plane_tile_pad<T, N3>()>(N2) * (SPLIT ? (int)sizeof(T) : 2 * (int)sizeof(T));
   // transforms along i3, one per row.  On the compact (unpadded) tile the
-  // rows take the larger radix first: the first row pass then writes column
-  // R1 i + r from lane i (for 96: 12 i + r), which with the lanes of a row
-  // pass and the odd row stride lands every lane of a wave in its own bank.
+  // rows take the larger radix first: a forward first row pass then writes
+  // column R1 i + r from lane i (for 96: 12 i + r), which with the odd row
+  // stride gives each of 32 lanes served together its own pair of banks.
   using Rw = std::conditional_t<plane_tile_pad<T, N3>(), Axis<N3, N2, true, W>,
                                 Axis<N3, N2, true, W, Factor<N3>::R1, Factor<N3>::R0>>;
   using Cl = Axis<N2, N3, false, W>;  // transforms along i2, one per column
@@ -198,8 +198,8 @@ __device__ __forceinline__ void plane_body(const PlaneArgs& A, int lid, unsigned
   // On the compact (unpadded) tile, the row pass that touches only LDS walks
   // the rows with its lanes: the forward direction's second row pass, the
   // backward direction's first.  Its exchanges then spread the lanes of a
-  // wave over rows (stride COLS + 1) instead of a row's 8-element-strided
-  // columns, and stall on far fewer bank conflicts.  The V-multiply mode,
+  // wave over 32 rows at the odd stride COLS + 1, one bank pair each,
+  // instead of over strided columns of a few rows.  The V-multiply mode,
   // whose row passes also meet V(r) in HBM, keeps the default order.
   constexpr bool fwd_dir = MODE == PLANE_PAIR_FWD || MODE == PLANE_PAIR_FWD_G || MODE == PLANE_FWD;
   constexpr bool rows_lb = !PAD && MODE != PLANE_VMUL;
