@@ -61,3 +61,27 @@ def test_step_bytes_tile_structure():
     lf = 0.75
     b2, _ = bench.step_bytes(128, 1, 1, True, sched=2, lf=lf)["p2_pencil_kernel"]
     assert abs(b2 - (1 + lf) * (28 * 256 + 8 * 136)) < 1e-9
+
+
+def test_roofline_picks_the_dominant_class_and_its_bound(monkeypatch):
+    """The roofline record: the class with the most time is reported; it is
+    measured against the vector-ALU peak when its algorithmic intensity is
+    above the ridge point (78.6 TFLOP/s / 8 TB/s), else against HBM; every
+    pair-pass class is listed against the plain-copy rate."""
+    monkeypatch.setattr(bench, "copy_gbs", lambda: 5000.0)
+    monkeypatch.setattr(bench, "pmc_traffic", lambda workload, kernel_class: None)
+    # ms over the run and launches per class; bytes and flops per step
+    tr = {"p1_pair_plane_fwd": [300.0, 1000], "p2_pencil_kernel": [290.0, 1000], "p3_second": [230.0, 1000]}
+    acc = {"p1_pair_plane_fwd": [7.0e11, 1000], "p2_pencil_kernel": [1.4e12, 1000], "p3_second": [1.1e12, 1000]}
+    flops = {"p1_pair_plane_fwd": 7.0e12, "p2_pencil_kernel": 6.5e12, "p3_second": 1.6e12}
+    rec = bench.roofline(tr, acc, 1, "c4_fp32_batched", fp64=False, flops=flops)
+    assert rec["kernel"] == "p1_pair_plane_fwd" and rec["bound"] == "alu" and rec["unit"] == "TFLOP/s"
+    assert abs(rec["achieved"] - 7.0e12 / 0.3 / 1e12) < 0.01
+    assert abs(rec["frac"] - rec["achieved"] / bench.VALU_PEAK_TFLOPS) < 1e-3
+    assert abs(rec["hbm_gbs"] - 7.0e11 / 0.3 / 1e9) < 0.1
+    assert set(rec["classes"]) == set(tr) and abs(rec["classes"]["p2_pencil_kernel"]["vs_copy"] - 1.4e12 / 0.29 / 1e9 / 5000.0) < 1e-3
+    # P1 faster than P2: P2 dominates, and its intensity (4.6 flop/B) lies below the ridge
+    tr["p1_pair_plane_fwd"] = [280.0, 1000]
+    rec = bench.roofline(tr, acc, 1, "c4_fp32_batched", fp64=False, flops=flops)
+    assert rec["kernel"] == "p2_pencil_kernel" and rec["bound"] == "hbm" and rec["unit"] == "GB/s"
+    assert abs(rec["frac"] - 1.4e12 / 0.29 / 1e9 / bench.HBM_PEAK_GBS) < 1e-3
