@@ -46,7 +46,12 @@ HBM_PEAK_GBS = 8000.0
 VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 METRIC = "band-pair Fock applications/sec and HBM GB/s at 1 GPU, FP32-batched vs FP64 plain"
 UNIT = "band-pair applications/s"
-MAC_TILE = 16  # pair tile edge of the library's schedules
+
+
+def pair_tile(fp64):
+    """Pair tile edge of the library's single-system schedules: 16 x 16 pairs
+    in FP64, 32 x 32 in FP32."""
+    return 16 if fp64 else 32
 
 WORKLOADS = {
     "c2_fp64": "64^3 cubic L=20 bohr, 128 orbitals applied to themselves, FP64 (16384 pairs)",
@@ -157,7 +162,8 @@ def cpu_baseline_bands(s, c, w, v, force):
 
 # ---------------------------------------------------------------------------
 # Algorithmic bytes of each kernel class over one step (units of N*b).
-# Mirrors the library's schedules: tiles of up to 16 x 16 pairs; one orbital
+# Mirrors the library's schedules: tiles of up to 16 x 16 pairs in FP64 and
+# 32 x 32 in FP32 (pair_tile); one orbital
 # block at q = 0 runs the pair-symmetric schedule (tiles I <= J, diagonal
 # tiles holding only the pairs ii <= jj): FP64 planes up to 64 wide use a
 # fused inverse + multiply-accumulate for each mirror half (the transform is
@@ -212,7 +218,7 @@ def pair_flops(n):
 def step_bytes(nb, N, bpc, fp64, sym=True, sched=None, lf=1.0, n=None, flops=None):
     """Algorithmic bytes (and, with n and a dict `flops`, flops) of each kernel
     class over one step: {class: [bytes, launches]}."""
-    T = min(MAC_TILE, nb)
+    T = min(pair_tile(fp64), nb)
     if sched is None:
         sched = 2 if fp64 else 1
     acc = {}
@@ -529,25 +535,27 @@ def gamma_block(name, args, cpu):
     return rec
 
 
-def tile_bytes(lf):
-    """Algorithmic bytes per launch of each class on full 16 x 16 tiles (units
+def tile_bytes(lf, e=32):
+    """Algorithmic bytes per launch of each class on full e x e tiles (units
     of N*b), for the k-mesh workload in FP32 (schedule 1): P3 is the in-place
     inverse plane FFT of the tile, the second pass the streaming MAC of both
     halves (pair buffer, both orbital tiles, both accumulator tiles read and
     written).  lf: live fraction of the pair-buffer columns."""
-    return {"p1_pair_plane_fwd": 16 + 16 + 256 * lf, "p2_pencil_energy": 256 * lf, "p2_pencil_kernel": 256 * lf + 256,
-            "p3_plane_inv_mac": 256 * lf + 256, "p3_second": 256 + 16 + 16 + 32 + 32}
+    p = e * e
+    return {"p1_pair_plane_fwd": 2 * e + p * lf, "p2_pencil_energy": p * lf, "p2_pencil_kernel": p * lf + p,
+            "p3_plane_inv_mac": p * lf + p, "p3_second": p + 2 * e + 4 * e}
 
 
-def tile_flops(n):
-    """Algorithmic flops per launch and grid point of each class on full 16 x
-    16 tiles, for the k-mesh workload (pair_flops per pair times 256 pairs;
-    the streaming MAC accumulates both halves)."""
+def tile_flops(n, e=32):
+    """Algorithmic flops per launch and grid point of each class on full e x e
+    tiles, for the k-mesh workload (pair_flops per pair times e^2 pairs; the
+    streaming MAC accumulates both halves)."""
     pf = pair_flops(n)
     l1 = float(np.log2(n[0]))
-    return {"p1_pair_plane_fwd": 256 * pf["p1_pair_plane_fwd"], "p2_pencil_kernel": 256 * pf["p2_pencil_kernel"],
-            "p2_pencil_energy": 256 * (5 * l1 + 4), "p3_plane_inv_mac": 256 * pf["p3_inplace"],
-            "p3_second": 256 * 2 * pf["mac_half"]}
+    p = e * e
+    return {"p1_pair_plane_fwd": p * pf["p1_pair_plane_fwd"], "p2_pencil_kernel": p * pf["p2_pencil_kernel"],
+            "p2_pencil_energy": p * (5 * l1 + 4), "p3_plane_inv_mac": p * pf["p3_inplace"],
+            "p3_second": p * 2 * pf["mac_half"]}
 
 
 def kmesh_grad(name, args, cpu):

@@ -344,16 +344,17 @@ fock_status get_plan(const fock_cell* cell, int dtype, std::shared_ptr<Plan>* ou
 // ---------------------------------------------------------------------------
 // Tiling and workspace layout
 // ---------------------------------------------------------------------------
-constexpr int kTileDefault = 16;
 constexpr int kGbParts = 512;
 
 struct Tiles {
   int ti, tj;
 };
-Tiles tiles_for(int n_occ, int n_tgt) {
+// Pair tile of a job: edge pair_tile(element size), or the whole block when smaller.
+Tiles tiles_for(int n_occ, int n_tgt, int cplx_bytes) {
+  const int edge = pair_tile(cplx_bytes);
   Tiles t;
-  t.ti = n_occ < kTileDefault ? (n_occ > 0 ? n_occ : 1) : kTileDefault;
-  t.tj = n_tgt < kTileDefault ? (n_tgt > 0 ? n_tgt : 1) : kTileDefault;
+  t.ti = n_occ < edge ? (n_occ > 0 ? n_occ : 1) : edge;
+  t.tj = n_tgt < edge ? (n_tgt > 0 ? n_tgt : 1) : edge;
   return t;
 }
 
@@ -366,7 +367,7 @@ struct Layout {
 Layout layout(long long N, int cplx_bytes, int ngroups, int n_occ, int n_tgt) {
   // Sized for both role orders (the backward pass swaps the blocks).
   const int nmax = n_occ > n_tgt ? n_occ : n_tgt;
-  const Tiles t = tiles_for(nmax, nmax);
+  const Tiles t = tiles_for(nmax, nmax, cplx_bytes);
   const size_t nb = (size_t)N * cplx_bytes;
   const int nt_i = (n_occ + t.ti - 1) / t.ti, nt_j = (n_tgt + t.tj - 1) / t.tj;
   const int ntiles = (nt_i > 0 ? nt_i : 1) * (nt_j > 0 ? nt_j : 1);
@@ -407,7 +408,7 @@ Layout layout_gamma(long long N, int cplx_bytes, int nb) {
 // k-mesh jobs: every set's real-space orbitals stay resident; one
 // accumulator block; tile partials for every (k <= k') block.
 Layout layout_kmesh(long long N, int cplx_bytes, int ngroups, int nk, int nbmax) {
-  const Tiles t = tiles_for(nbmax, nbmax);
+  const Tiles t = tiles_for(nbmax, nbmax, cplx_bytes);
   const size_t nb = (size_t)N * cplx_bytes;
   const int ntb = (nbmax + t.ti - 1) / t.ti;
   const int ntiles = (nk * (nk + 1) / 2) * (ntb > 0 ? ntb * ntb : 1);
@@ -662,7 +663,7 @@ struct Engine {
   };
 
   fock_status pairs(const KernelParams& kp, char* ws, const Layout& L, const PairJob& J, int* ntiles) {
-    const Tiles t = tiles_for(J.nA, J.nB);
+    const Tiles t = tiles_for(J.nA, J.nB, (int)sizeof(cx<T>));
     void* w = ws + L.w;
     double* epart = reinterpret_cast<double*>(ws + L.epart);
     double* tile_e = reinterpret_cast<double*>(ws + L.tile_e) + J.tile_base;
@@ -672,7 +673,7 @@ struct Engine {
     if (J.cross) {
       if (J.energy || J.sym || !J.acc_full || !J.acc_mirror || !J.fB || sym_schedule() == 0)
         return fail(FOCK_E_ARG, "internal: bad cross-block job");
-      const int T0 = t.ti < kMacTile ? t.ti : kMacTile;
+      const int T0 = t.ti;  // the pair tile edge (tiles_for), or the whole block
       for (int j0 = 0; j0 < J.nB; j0 += T0) {
         const int tj = (J.nB - j0) < T0 ? (J.nB - j0) : T0;
         for (int i0 = 0; i0 < J.nA; i0 += T0) {
@@ -778,7 +779,7 @@ struct Engine {
     }
     // symmetric schedule
     if (!J.energy && !J.acc_full) return fail(FOCK_E_ARG, "internal: symmetric apply needs full accumulators");
-    const int T0 = t.ti < kMacTile ? t.ti : kMacTile;
+    const int T0 = t.ti;  // the pair tile edge (tiles_for), or the whole block
     void* acc_all = J.acc_full;
     const void* phiA = J.phiA;
     for (int j0 = 0; j0 < J.nB; j0 += T0) {
@@ -867,12 +868,6 @@ struct Engine {
   }
 };
 
-// number of energy tiles a job produces
-int energy_tiles(int nA, int nB, bool sym) {
-  const Tiles t = tiles_for(nA, nB);
-  const int nti = (nA + t.ti - 1) / t.ti, ntj = (nB + t.tj - 1) / t.tj;
-  return sym ? nti * (nti + 1) / 2 : nti * ntj;
-}
 
 template <typename T>
 fock_status apply_impl(const fock_cell* cell, const Plan& P, const double q[3], bool q_zero, const fock_orbs* occ,

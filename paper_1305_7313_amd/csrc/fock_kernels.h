@@ -721,10 +721,17 @@ struct MacArgs {
   int tri;             // diagonal tile: pairs ii <= jj at tri_slot(ii, jj); forward ii <= jj, mirror ii < jj
 };
 
-constexpr int kMacTile = 16;
+constexpr int kMacTile = 16;  // the persistent batch schedule's and the Gamma path's tile edge
+
+// Pair tile edge of the single-system schedules, by element size: 32 x 32
+// pairs for complex FP32 (the streaming MAC then moves 1.19 N b per pair
+// instead of 1.38), 16 x 16 for complex FP64, whose MAC registers would not
+// hold 32 accumulators.
+constexpr int pair_tile(int cplx_bytes) { return cplx_bytes == 8 ? 32 : 16; }
 
 template <typename T>
 __global__ __launch_bounds__(256) void mac_pair_kernel(MacArgs A) {
+  constexpr int TILE = pair_tile((int)sizeof(cx<T>));
   const long long N = A.N;
   const long long p = (long long)blockIdx.x * 256 + threadIdx.x;
   if (p >= N) return;
@@ -738,9 +745,9 @@ __global__ __launch_bounds__(256) void mac_pair_kernel(MacArgs A) {
   cx<T>* acc_b = reinterpret_cast<cx<T>*>(A.acc_b) + p;
   const double* __restrict__ f_b = A.f_b;
   const int ti = A.ti, tj = A.tj, mirror = A.mirror, tri = A.tri;
-  cx<T> fphi_i[kMacTile], acc_i[kMacTile];
+  cx<T> fphi_i[TILE], acc_i[TILE];
 #pragma unroll
-  for (int ii = 0; ii < kMacTile; ++ii) {
+  for (int ii = 0; ii < TILE; ++ii) {
     if (ii < ti) fphi_i[ii] = cscale<T>(phi[(long long)(A.i0 + ii) * N], T(f[A.i0 + ii]));
     acc_i[ii] = mk<T>(T(0), T(0));
   }
@@ -750,13 +757,13 @@ __global__ __launch_bounds__(256) void mac_pair_kernel(MacArgs A) {
     // the forward half alone (mirror == 0) reads neither phi_b nor f_b
     const cx<T> fphi_j = mirror ? cscale<T>(phi_b[oj], T(f_b[A.j0 + jj])) : mk<T>(T(0), T(0));
     const int iend = tri ? jj + 1 : ti;  // forward: ii < iend; mirror: ii < jj on a diagonal tile
-    cx<T> v[kMacTile];
+    cx<T> v[TILE];
 #pragma unroll
-    for (int ii = 0; ii < kMacTile; ++ii)
+    for (int ii = 0; ii < TILE; ++ii)
       if (ii < iend) v[ii] = load_stream<T>(&w[(long long)(tri ? tri_slot(ii, jj) : ii * tj + jj) * N]);
     T sx = aj0.x, sy = aj0.y;
 #pragma unroll
-    for (int ii = 0; ii < kMacTile; ++ii) {
+    for (int ii = 0; ii < TILE; ++ii) {
       if (ii < iend) {
         const cx<T> a = cmul<T>(fphi_i[ii], v[ii]);
         sx += a.x;
@@ -771,7 +778,7 @@ __global__ __launch_bounds__(256) void mac_pair_kernel(MacArgs A) {
   }
   if (mirror) {
 #pragma unroll
-    for (int ii = 0; ii < kMacTile; ++ii) {
+    for (int ii = 0; ii < TILE; ++ii) {
       if (ii < ti) {
         const long long oi = (long long)(A.i0 + ii) * N;
         const cx<T> c = acc[oi];
