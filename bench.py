@@ -49,9 +49,18 @@ UNIT = "band-pair applications/s"
 
 
 def pair_tile(fp64):
-    """Pair tile edge of the library's single-system schedules: 16 x 16 pairs
-    in FP64, 32 x 32 in FP32."""
+    """Largest pair tile edge of the library's single-system schedules: 16 x
+    16 pairs in FP64, 32 x 32 in FP32."""
     return 16 if fp64 else 32
+
+
+def balanced_edge(n, edge):
+    """The library's tile edge for a block of n orbitals: the fewest tiles of
+    at most `edge`, of near-equal size."""
+    if n <= 0:
+        return 1
+    parts = -(-n // edge)
+    return -(-n // parts)
 
 WORKLOADS = {
     "c2_fp64": "64^3 cubic L=20 bohr, 128 orbitals applied to themselves, FP64 (16384 pairs)",
@@ -218,7 +227,7 @@ def pair_flops(n):
 def step_bytes(nb, N, bpc, fp64, sym=True, sched=None, lf=1.0, n=None, flops=None):
     """Algorithmic bytes (and, with n and a dict `flops`, flops) of each kernel
     class over one step: {class: [bytes, launches]}."""
-    T = min(pair_tile(fp64), nb)
+    T = balanced_edge(nb, pair_tile(fp64))
     if sched is None:
         sched = 2 if fp64 else 1
     acc = {}

@@ -349,14 +349,27 @@ constexpr int kGbParts = 512;
 struct Tiles {
   int ti, tj;
 };
-// Pair tile of a job: edge pair_tile(element size), or the whole block when smaller.
+// Pair tile of a job: the block split into the fewest tiles of at most
+// pair_tile(element size) orbitals, of near-equal size (174 orbitals at edge
+// 32: tiles of 29, not five of 32 and one of 14), so that no launch carries
+// a thin remainder.
+int balanced_edge(int n, int edge) {
+  if (n <= 0) return 1;
+  const int parts = (n + edge - 1) / edge;
+  return (n + parts - 1) / parts;
+}
 Tiles tiles_for(int n_occ, int n_tgt, int cplx_bytes) {
   const int edge = pair_tile(cplx_bytes);
   Tiles t;
-  t.ti = n_occ < edge ? (n_occ > 0 ? n_occ : 1) : edge;
-  t.tj = n_tgt < edge ? (n_tgt > 0 ? n_tgt : 1) : edge;
+  t.ti = balanced_edge(n_occ, edge);
+  t.tj = balanced_edge(n_tgt, edge);
   return t;
 }
+// Workspace bounds for any job on blocks of up to nmax orbitals: no tile edge
+// exceeds min(nmax, edge) (the balanced edge is not monotonic in n), and a
+// block of n orbitals has ceil(n / edge) tiles along it.
+int tile_cap(int nmax, int cplx_bytes) { return std::max(1, std::min(nmax, pair_tile(cplx_bytes))); }
+int tile_count(int n, int cplx_bytes) { return n > 0 ? (n + pair_tile(cplx_bytes) - 1) / pair_tile(cplx_bytes) : 1; }
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -367,17 +380,16 @@ struct Layout {
 Layout layout(long long N, int cplx_bytes, int ngroups, int n_occ, int n_tgt) {
   // Sized for both role orders (the backward pass swaps the blocks).
   const int nmax = n_occ > n_tgt ? n_occ : n_tgt;
-  const Tiles t = tiles_for(nmax, nmax, cplx_bytes);
+  const int tc = tile_cap(nmax, cplx_bytes);
   const size_t nb = (size_t)N * cplx_bytes;
-  const int nt_i = (n_occ + t.ti - 1) / t.ti, nt_j = (n_tgt + t.tj - 1) / t.tj;
-  const int ntiles = (nt_i > 0 ? nt_i : 1) * (nt_j > 0 ? nt_j : 1);
+  const int ntiles = tile_count(n_occ, cplx_bytes) * tile_count(n_tgt, cplx_bytes);
   Layout L;
   size_t off = 0;
   L.phiA = off; off += align_up(nb * (size_t)nmax);
   L.phiB = off; off += align_up(nb * (size_t)nmax);
-  L.acc = off; off += align_up(nb * (size_t)t.tj);
-  L.w = off; off += align_up(nb * (size_t)t.ti * t.tj);
-  L.epart = off; off += align_up(sizeof(double) * (size_t)t.ti * t.tj * ngroups);
+  L.acc = off; off += align_up(nb * (size_t)tc);
+  L.w = off; off += align_up(nb * (size_t)tc * tc);
+  L.epart = off; off += align_up(sizeof(double) * (size_t)tc * tc * ngroups);
   L.tile_e = off; off += align_up(sizeof(double) * (size_t)ntiles);
   L.k0 = off; off += align_up(sizeof(double));
   L.gbpart = off; off += align_up(sizeof(double) * kGbParts);
@@ -408,10 +420,10 @@ Layout layout_gamma(long long N, int cplx_bytes, int nb) {
 // k-mesh jobs: every set's real-space orbitals stay resident; one
 // accumulator block; tile partials for every (k <= k') block.
 Layout layout_kmesh(long long N, int cplx_bytes, int ngroups, int nk, int nbmax) {
-  const Tiles t = tiles_for(nbmax, nbmax, cplx_bytes);
+  const int tc = tile_cap(nbmax, cplx_bytes);
   const size_t nb = (size_t)N * cplx_bytes;
-  const int ntb = (nbmax + t.ti - 1) / t.ti;
-  const int ntiles = (nk * (nk + 1) / 2) * (ntb > 0 ? ntb * ntb : 1);
+  const int ntb = tile_count(nbmax, cplx_bytes);
+  const int ntiles = (nk * (nk + 1) / 2) * ntb * ntb;
   // tile_e also holds the per-band partials of the energy taken from the gradient
   const int nparts = ntiles > nk * nbmax ? ntiles : nk * nbmax;
   Layout L;
@@ -420,9 +432,9 @@ Layout layout_kmesh(long long N, int cplx_bytes, int ngroups, int nk, int nbmax)
   // gradient accumulators of every k-point: one transform per pair feeds the
   // blocks (k, k') and (k', k)
   L.phiB = off; off += align_up(nb * (size_t)nbmax * nk);
-  L.acc = off; off += align_up(nb * (size_t)t.tj);
-  L.w = off; off += align_up(nb * (size_t)t.ti * t.tj);
-  L.epart = off; off += align_up(sizeof(double) * (size_t)t.ti * t.tj * ngroups);
+  L.acc = off; off += align_up(nb * (size_t)tc);
+  L.w = off; off += align_up(nb * (size_t)tc * tc);
+  L.epart = off; off += align_up(sizeof(double) * (size_t)tc * tc * ngroups);
   L.tile_e = off; off += align_up(sizeof(double) * (size_t)nparts);
   L.k0 = off; off += align_up(sizeof(double));
   L.gbpart = off; off += align_up(sizeof(double) * kGbParts);
