@@ -249,11 +249,12 @@ def step_bytes(nb, N, bpc, fp64, sym=True, sched=None, lf=1.0, n=None, flops=Non
             tri = diag and sched != 0
             npr = ti * (ti + 1) // 2 if tri else ti * tj
             # P1 stores and P2 reads only the live columns (fraction lf); P2
-            # writes the whole pairs, zeros included
+            # writes the dead columns' zeros only for the fused P3 passes
+            # (schedules 0 and 2), which read every column
             f = pf or {k: 0.0 for k in ("p1_pair_plane_fwd", "p2_pencil_kernel", "p3_inplace", "p3_fused", "mac_half")}
             nmir = (ti * (ti - 1) // 2 if tri else 0) if diag else ti * tj  # pairs of the mirror half
             add("p1_pair_plane_fwd", ti + (0 if diag else tj), npr * lf, fl=npr * f["p1_pair_plane_fwd"])
-            add("p2_pencil_kernel", npr * lf, npr, fl=npr * f["p2_pencil_kernel"])
+            add("p2_pencil_kernel", npr * lf, npr * lf if sym and sched == 1 else npr, fl=npr * f["p2_pencil_kernel"])
             if not sym:
                 add("p3_plane_inv_mac", ti * tj + ti + tj, tj, fl=npr * f["p3_fused"])
             elif sched in (0, 2):  # fused P3 into acc_J; mirror: recomputed (2) or from v written back (0)
@@ -292,7 +293,7 @@ def gamma_step_bytes(n, N, bpc, ti_max=16, tj_max=8, lf=1.0):
             # diagonal tile: only the pairs i <= 2q + 1 (non-zero weight)
             npr = sum(min(ti, 2 * jj + 2) for jj in range(tj)) if i0 == 2 * j0 else ti * tj
             add("p1_pair_plane_fwd", pi + tj, npr * lf)
-            add("p2_pencil_kernel", npr * lf, npr)
+            add("p2_pencil_kernel", npr * lf, npr * lf)  # both Gamma schedules mask the dead columns
             add("p3_plane_inv_mac", npr * lf + pi + tj, tj)
             add("p3_second", npr * lf + tj + pi, pi)
     return acc
@@ -551,7 +552,7 @@ def tile_bytes(lf, e=32):
     halves (pair buffer, both orbital tiles, both accumulator tiles read and
     written).  lf: live fraction of the pair-buffer columns."""
     p = e * e
-    return {"p1_pair_plane_fwd": 2 * e + p * lf, "p2_pencil_energy": p * lf, "p2_pencil_kernel": p * lf + p,
+    return {"p1_pair_plane_fwd": 2 * e + p * lf, "p2_pencil_energy": p * lf, "p2_pencil_kernel": 2 * p * lf,
             "p3_plane_inv_mac": p * lf + p, "p3_second": p + 2 * e + 4 * e}
 
 

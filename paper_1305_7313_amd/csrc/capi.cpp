@@ -548,8 +548,10 @@ struct Engine {
   }
 
   // P1 and P2 of one pair tile (energy: P2 only accumulates partials).
+  // masked_reader: every pass that reads this pair buffer after P2 masks the
+  // dead columns, so P2 need not write their zeros.
   fock_status tile_forward(const PlaneArgs& la, const KernelParams& kp, bool energy, double* epart,
-                           int p1_mode = PLANE_PAIR_FWD) {
+                           int p1_mode, bool masked_reader) {
     const int tt = !la.tri ? la.ti * la.tj : p1_mode == PLANE_PAIR_FWD_G ? gtri_prefix(la.ti, la.tj) : tri_slot(0, la.ti);
     {
       FX_TRACE(KC_P1);
@@ -565,6 +567,7 @@ struct Engine {
     pa.n2 = P.n[1];
     pa.n3 = P.n[2];
     pa.count = tt;
+    pa.skip_dead = masked_reader ? 1 : 0;
     if (energy) {
       FX_TRACE(KC_P2E);
       FX_HIP(launch_pencil<T>(PENCIL_FE, P.n[0], pa, tt * ngroups, s));
@@ -692,7 +695,9 @@ struct Engine {
           const int ti = (J.nA - i0) < T0 ? (J.nA - i0) : T0;
           PlaneArgs la = plane_args(J.phiA, J.phiB, w, nullptr, J.fA, i0, j0, ti, tj);
           la.live = live();
-          if ((st = tile_forward(la, kp, false, nullptr)) != FOCK_OK) return st;
+          // schedule 2 reads the pairs in the fused passes (every column), else
+          // the in-place inverse reads them (live columns only)
+          if ((st = tile_forward(la, kp, false, nullptr, PLANE_PAIR_FWD, sym_schedule() != 2)) != FOCK_OK) return st;
           if (sym_schedule() == 2) {
             PlaneArgs lp = la;
             lp.acc = static_cast<char*>(J.acc_full) + (size_t)j0 * box;
@@ -748,7 +753,8 @@ struct Engine {
           const int ti = (J.nA - i0) < t.ti ? (J.nA - i0) : t.ti;
           PlaneArgs la = plane_args(J.phiA, J.phiB, w, acc, J.fA, i0, j0, ti, tj);
           la.live = live();
-          if ((st = tile_forward(la, kp, J.energy, epart)) != FOCK_OK) return st;
+          if ((st = tile_forward(la, kp, J.energy, epart, PLANE_PAIR_FWD, apply_schedule() == 1)) != FOCK_OK)
+            return st;
           if (J.energy) {
             FX_TRACE(KC_REDUCE);
             FX_HIP(launch_energy_tile(epart, ngroups, J.fA, J.gB, i0, j0, ti, tj, 0, 0, J.escale, tile_e + tile, s));
@@ -805,7 +811,7 @@ struct Engine {
         // reduction counts the off-diagonal pairs twice
         la.tri = i0 == j0 && ti == tj && (J.energy || sym_schedule() != 0);
         const int tt = la.tri ? tri_slot(0, ti) : ti * tj;
-        if ((st = tile_forward(la, kp, J.energy, epart)) != FOCK_OK) return st;
+        if ((st = tile_forward(la, kp, J.energy, epart, PLANE_PAIR_FWD, sym_schedule() == 1)) != FOCK_OK) return st;
         if (J.energy) {
           FX_TRACE(KC_REDUCE);
           FX_HIP(launch_energy_tile(epart, ngroups, J.fA, J.gB, i0, j0, ti, tj, 1, la.tri, J.escale, tile_e + tile, s));
@@ -963,7 +969,8 @@ fock_status apply_gamma_impl(const fock_cell* cell, const Plan& P, const fock_or
       // pairs with a non-zero weight, i <= 2q + 1, are transformed
       la.tri = i0 == 2 * j0;
       const int tt = la.tri ? gtri_prefix(ti, tj) : ti * tj;
-      if ((st = E.tile_forward(la, kp, false, nullptr, PLANE_PAIR_FWD_G)) != FOCK_OK) return st;
+      // both Gamma schedules mask the dead columns when they read the pairs
+      if ((st = E.tile_forward(la, kp, false, nullptr, PLANE_PAIR_FWD_G, true)) != FOCK_OK) return st;
       if (E.gamma_schedule() == 1) {
         {
           FX_TRACE(KC_P3);

@@ -135,6 +135,8 @@ struct PencilArgs {
   KernelParams kp;
   long long N;
   int n2, n3, count;   // count = pairs or orbitals
+  int skip_dead;       // PENCIL_FKI with live: 1 leaves the lines of wholly dead columns
+                       // unwritten (every reader of this buffer masks them); 0 writes the zeros
 };
 
 // Hardware dispatches workgroup w to XCD (w mod 8).  Renumber so that
@@ -593,8 +595,9 @@ __device__ __forceinline__ void pencil_body(const PencilArgs& A, int lid, unsign
   // (row, col) of the tile = (i1, column c0 + col).  A column pass: every
   // value of this thread is in column c0 + t % CB.  In pair buffers (live
   // set) P1 has not stored the dead columns: those pencils are not read and
-  // transform as zero, and the zeros are written (the fused P3 passes read
-  // every column).
+  // transform as zero.  Their zeros are written unless skip_dead is set: the
+  // fused P3 passes read every column, the in-place inverse reads only the
+  // live ones.
   constexpr int DIR0 = (MODE == PENCIL_INV) ? +1 : -1;
   bool live = true;
   if (A.live) {
@@ -674,7 +677,20 @@ __device__ __forceinline__ void pencil_body(const PencilArgs& A, int lid, unsign
       pass_compute<P0, +1, T>(v, tw1, t);
       exchange<P0, P1, CB, SPLIT, T>(v, smem, t);
       pass_compute<P1, +1, T>(v, tw1, t);
-      for_outputs<P1>(t, [&](int e, int row, int col) { store_stream<T>(&base[(long long)row * plane + col], v[e]); });
+      // skip_dead: a 128-byte line of a row is left unwritten when every
+      // column in it is dead; a partly live line is written whole (zeros
+      // included), since a partial line costs the memory a read-modify-write.
+      // A wave's lanes hold consecutive columns from a multiple of CB, so the
+      // LINE lanes of an aligned lane group hold one line.
+      bool st = true;
+      if (A.live && A.skip_dead) {
+        constexpr int LINE = 128 / (int)sizeof(cx<T>);
+        static_assert(CB % LINE == 0 && (CB % 64 == 0 || 64 % CB == 0), "lines of whole lane groups");
+        const unsigned long long m = __ballot(live);
+        st = ((m >> ((threadIdx.x & 63) & ~(LINE - 1))) & ((1ull << LINE) - 1)) != 0;
+      }
+      if (st)
+        for_outputs<P1>(t, [&](int e, int row, int col) { store_stream<T>(&base[(long long)row * plane + col], v[e]); });
     }
   }
 }

@@ -61,6 +61,10 @@ def test_step_bytes_tile_structure():
     lf = 0.75
     b2, _ = bench.step_bytes(128, 1, 1, True, sched=2, lf=lf)["p2_pencil_kernel"]
     assert abs(b2 - (1 + lf) * (28 * 256 + 8 * 136)) < 1e-9
+    # schedule 1: the in-place inverse masks the dead columns, so P2 writes
+    # only the live ones
+    b3, _ = bench.step_bytes(128, 1, 1, True, sched=1, lf=lf)["p2_pencil_kernel"]
+    assert abs(b3 - 2 * lf * (28 * 256 + 8 * 136)) < 1e-9
 
 
 def test_roofline_picks_the_dominant_class_and_its_bound(monkeypatch):
