@@ -52,27 +52,45 @@ def stats(csv_path, out_md, command):
     open(out_md, "w").write("\n".join(lines) + "\n")
 
 
+def dispatch_classes(rows):
+    """Kernel class of every dispatch.  The in-place inverse plane pass runs in
+    two roles: after P2 it is the pair pass P3 of the streaming schedule
+    (class p3_plane_inv_mac, like the fused P3), after the inverse pencil pass
+    it takes orbitals to real space (class plane_inv).  Its role is read from
+    the dispatch before it on the same queue (a stream's kernels run in order
+    on one queue)."""
+    out = {}
+    last = {}
+    for r in sorted(rows, key=lambda r: int(r["Dispatch_Id"])):
+        k = kernel_class(r["Kernel_Name"])
+        if k == "plane_inv" and last.get(r["Queue_Id"]) == "p2_pencil_kernel":
+            k = "p3_plane_inv_mac"
+        out[r["Dispatch_Id"]] = k
+        last[r["Queue_Id"]] = k
+    return out
+
+
 def traffic(fetch_csv, write_csv, workload, out_json, command, sha):
     def load(p):
+        rows = list(csv.DictReader(open(p)))
+        cls = dispatch_classes(rows)
         agg = collections.defaultdict(list)
-        for r in csv.DictReader(open(p)):
-            agg[r["Kernel_Name"]].append(float(r["Counter_Value"]))
-        return agg
-    f, w = load(fetch_csv), load(write_csv)
-    cf = sum(f.get("__amd_rocclr_copyBuffer", []))
-    cw = sum(w.get("__amd_rocclr_copyBuffer", []))
+        copy = 0.0
+        for r in rows:
+            if r["Kernel_Name"] == "__amd_rocclr_copyBuffer":
+                copy += float(r["Counter_Value"])
+            elif cls[r["Dispatch_Id"]]:
+                agg[cls[r["Dispatch_Id"]]].append(float(r["Counter_Value"]))
+        return agg, copy
+    (f, cf), (w, cw) = load(fetch_csv), load(write_csv)
     rec = {"workload": workload, "command": command, "source_sha256": sha,
            "fetch_scale": cw / cf if cf else None, "write_scale": COPY_BYTES / 1024.0 / cw if cw else None,
            "copy_probe": {"bytes": COPY_BYTES, "fetch_kib": cf, "write_kib": cw}, "kernels": {}}
     by_class = collections.defaultdict(lambda: [[], []])
-    for name, vals in f.items():
-        k = kernel_class(name)
-        if k:
-            by_class[k][0].extend(vals)
-    for name, vals in w.items():
-        k = kernel_class(name)
-        if k:
-            by_class[k][1].extend(vals)
+    for k, vals in f.items():
+        by_class[k][0].extend(vals)
+    for k, vals in w.items():
+        by_class[k][1].extend(vals)
     for k, (fv, wv) in by_class.items():
         rec["kernels"][k] = {"dispatches": len(fv), "fetch_kib": sum(fv) / len(fv), "write_kib": sum(wv) / len(wv)}
     open(out_json, "w").write(json.dumps(rec, indent=1) + "\n")

@@ -7,6 +7,8 @@
 * The per-launch pair counts of the symmetric schedule reproduce the tile
   structure: 36 launches and 8256 transformed pairs for 128 orbitals, the
   figures the PMC traffic of config 2 was checked against.
+* The counter summary tells the in-place inverse plane pass after P2 (the
+  P3 class) from the same kernel taking orbitals to real space.
 """
 import numpy as np
 
@@ -89,3 +91,33 @@ def test_roofline_picks_the_dominant_class_and_its_bound(monkeypatch):
     rec = bench.roofline(tr, acc, 1, "c4_fp32_batched", fp64=False, flops=flops)
     assert rec["kernel"] == "p2_pencil_kernel" and rec["bound"] == "hbm" and rec["unit"] == "GB/s"
     assert abs(rec["frac"] - 1.4e12 / 0.29 / 1e9 / bench.HBM_PEAK_GBS) < 1e-3
+
+
+def test_traffic_summary_splits_the_inverse_plane_pass_by_role(tmp_path):
+    """The in-place inverse plane pass after P2 on a queue is the P3 class;
+    after the inverse pencil pass it is the orbital transform.  Two queues
+    interleave as graph branches do; the copy probe sets the scales."""
+    from paper_1305_7313_amd import profsum
+    pl = "void fockx::plane_kernel<float, 96, 96, 768, true, {m}, 1>(fockx::PlaneArgs)"
+    pe = "void fockx::pencil_kernel<float, 96, 64, 512, false, {m}, 1>(fockx::PencilArgs)"
+    seq = [(1, pe.format(m=3), 10), (1, pl.format(m=3), 20),          # orbitals, queue 1
+           (2, pe.format(m=3), 10), (1, pl.format(m=0), 30),
+           (2, pl.format(m=3), 20), (1, pe.format(m=0), 40),          # orbitals, queue 2
+           (2, pl.format(m=0), 30), (1, pl.format(m=3), 50),          # P3 on queue 1
+           (2, pe.format(m=0), 40), (2, pl.format(m=3), 70),          # P3 on queue 2
+           (1, "__amd_rocclr_copyBuffer", 100)]
+    cols = ["Dispatch_Id", "Queue_Id", "Kernel_Name", "Counter_Value"]
+    path = tmp_path / "c.csv"
+    with open(path, "w") as fh:
+        fh.write(",".join(cols) + "\n")
+        for d, (q, name, v) in enumerate(seq):
+            fh.write(f'{d + 1},{q},"{name}",{v}\n')
+    out = tmp_path / "t.json"
+    profsum.traffic(str(path), str(path), "w", str(out), "cmd", "sha")
+    import json
+    rec = json.load(open(out))
+    k = rec["kernels"]
+    assert k["plane_inv"]["dispatches"] == 2 and k["plane_inv"]["fetch_kib"] == 20
+    assert k["p3_plane_inv_mac"]["dispatches"] == 2 and k["p3_plane_inv_mac"]["fetch_kib"] == 60
+    assert k["p2_pencil_kernel"]["dispatches"] == 2 and k["a1_pencil_inv"]["dispatches"] == 2
+    assert rec["fetch_scale"] == 1.0 and rec["copy_probe"]["fetch_kib"] == 100
