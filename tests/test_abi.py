@@ -59,6 +59,16 @@ def test_workspace_size(c1):
     assert F.fock_workspace_size(cell, 7, 8, 8) == 0
     bad = F.Cell(s.a, (24, 24, 25), s.miller)
     assert F.fock_workspace_size(bad, 0, 8, 8) == 0
+    # past the pair-tile edge (32 in FP32, 16 in FP64) the pair buffer and the
+    # accumulator tile stop growing: more orbitals only add their own planes
+    # (occupied and target real-space copies) while the tile count is unchanged
+    assert F.fock_workspace_size(cell, F.FOCK_C64, 40, 40) - F.fock_workspace_size(cell, F.FOCK_C64, 33, 33) \
+        == 2 * 7 * n * 8
+    assert F.fock_workspace_size(cell, F.FOCK_C128, 20, 20) - F.fock_workspace_size(cell, F.FOCK_C128, 17, 17) \
+        == 2 * 3 * n * 16
+    # below it the pair buffer holds a tile of min(n, edge)^2 pairs
+    assert F.fock_workspace_size(cell, F.FOCK_C64, 17, 17) - F.fock_workspace_size(cell, F.FOCK_C64, 16, 16) \
+        >= (2 + 1 + 17 * 17 - 16 * 16) * n * 8
 
 
 def test_error_codes(c1):
