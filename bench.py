@@ -30,6 +30,7 @@ import multiprocessing as mp
 import os
 import shutil
 import sys
+import tempfile
 import time
 
 import numpy as np
@@ -826,14 +827,15 @@ def main():
     ap.add_argument("--no-trace", action="store_true")
     ap.add_argument("--no-compare", action="store_true",
                     help="the batched workload without the config-2 FP64 record beside it")
-    ap.add_argument("--tune-cache", default=os.path.join(ROOT, "gpurun_out", "fock_tune_cache.json"))
+    ap.add_argument("--tune-cache", default=os.path.join(tempfile.gettempdir(), "fock_tune_cache.json"),
+                    help="tuned batch schedules (a missing file is seeded from the committed tune seed)")
     ap.add_argument("--no-tune-seed", action="store_true",
                     help="do not seed a missing tune cache from the committed one (forces a fresh tuning)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain device copy of known size (bandwidth-counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build runs on one GPU only; --gpus must be 1", file=sys.stderr)
+        print("bench.py: the exchange path runs on one GPU (no sharded form here); --gpus must be 1", file=sys.stderr)
         sys.exit(2)
     os.makedirs(os.path.dirname(args.tune_cache), exist_ok=True)
     seed_cache = os.path.join(ROOT, "paper_1305_7313_amd", "tune_seed.json")
